@@ -1,0 +1,227 @@
+/*
+ * mu.h -- C ABI of the MI355X (gfx950) muSR chi^2 / Poisson-likelihood library.
+ *
+ * The library evaluates, on the GPU, the cost that the fit of a set of
+ * positron histograms minimises (Locans et al., "Real-Time Computation of
+ * Parameter Fitting and Image Reconstruction Using Graphical Processing
+ * Units", Sec. 4):
+ *
+ *   N^j(t, P) = N0^j e^(-t/tau_mu) [1 + A^j(p^j, t)] + Nbkg^j        (Eq. 1)
+ *   chi^2(P)  = sum_j sum_n (d_n^j - N^j(t_n, P))^2 / v_n^j           (Eq. 2)
+ *   L(P)      = 2 sum_j sum_n [(N - d) + d ln(d / N)]                  (Eq. 3)
+ *
+ * with t_n = (n - t0_bin) dt (Eq. 1 text; t0_bin is 0 in the paper's
+ * statement), v = d for d > 0 and v = 1 for an empty bin (Eq. 2 gives
+ * d_err = sqrt(d); the empty-bin weight is this library's reading), and L
+ * minimised (it is the Poisson likelihood-ratio statistic; Eq. 3's "maximised"
+ * is read as a sign slip).  For d = 0 the likelihood term is 2N; for N <= 0 < d
+ * it is +inf.
+ *
+ * A^j(t) is a theory program: a sum of up to MU_MAX_TERMS terms, each
+ * coef * amp * prod of up to MU_MAX_FACTORS_PER_TERM primitives (Listing 2:
+ * se, ge, sg, stg; Listing 3: tf).  Every scalar argument is a reference that
+ * goes through the map row of the histogram: p[map[row][slot]], or the
+ * function array f[map[row][slot]] with f = F p + f0, or a literal.  This is
+ * the parameter / function / map indirection of Sec. 4.2.1 and Listing 3.
+ * Units: t in us, rates in 1/us, frequencies in MHz, phases in radians.
+ *
+ * Histograms are copied to the device once (mu_data_create) and stay there
+ * for the whole fit (Sec. 4.2: data sets do not change during the fit).
+ *
+ * Conventions of every entry point:
+ *   - every function returns a mu_status; nothing throws or aborts;
+ *   - on error no output is written and mu_ctx_last_error() names the cause;
+ *   - the caller owns every input and output buffer; *_create deep-copies
+ *     its inputs; a handle lives until its *_destroy;
+ *   - mem == MU_MEM_HOST: params and outputs are host pointers and the call
+ *     returns after the results are written (it synchronises the stream);
+ *     mem == MU_MEM_DEVICE: they are device pointers on the context's device,
+ *     the call only enqueues work on the context stream and returns;
+ *   - one host thread at a time per context;
+ *   - the same inputs give bitwise identical outputs (fixed-order reductions).
+ */
+#ifndef MU_H
+#define MU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MU_ABI_VERSION 1
+#define MU_MAX_TERMS 4
+#define MU_MAX_FACTORS_PER_TERM 3
+#define MU_MAX_PAR 1024
+
+typedef struct mu_ctx mu_ctx;
+typedef struct mu_data mu_data;
+typedef struct mu_theory mu_theory;
+typedef struct mu_seeder mu_seeder;
+
+typedef enum {
+  MU_OK = 0,
+  MU_E_ARG = 1,          /* invalid argument: nothing was done */
+  MU_E_NODEVICE = 2,     /* no usable GPU (or MU_FORCE_NODEVICE is set) */
+  MU_E_NOMEM = 3,        /* device or host allocation failed */
+  MU_E_DEVICE = 4,       /* a HIP call failed */
+  MU_E_UNSUPPORTED = 5,  /* valid request outside the library's limits */
+  MU_E_STATE = 6         /* handle in the wrong state (e.g. live children) */
+} mu_status;
+
+typedef enum { MU_COST_CHI2 = 0, MU_COST_POISSON = 1 } mu_cost;
+enum { MU_MEM_HOST = 0, MU_MEM_DEVICE = 1 };
+
+int mu_abi_version(void);
+const char *mu_status_string(mu_status s);
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t on
+ * that device that every call enqueues on (NULL: the context creates its own
+ * default-priority stream).  flags: reserved, pass 0.  Returns MU_E_NODEVICE
+ * when no device is visible or the environment variable MU_FORCE_NODEVICE is
+ * set to a non-empty value other than "0". */
+mu_status mu_ctx_create(int device, void *hip_stream, unsigned flags, mu_ctx **out);
+/* MU_E_STATE (and nothing freed) while data, theories or seeders created on
+ * this context are alive. */
+mu_status mu_ctx_destroy(mu_ctx *ctx);
+const char *mu_ctx_last_error(const mu_ctx *ctx);
+mu_status mu_ctx_synchronize(mu_ctx *ctx);
+
+/* -------------------------------------------------------------- histograms */
+
+/* One positron histogram (Sec. 4.1): counts d_n for n = 0 .. n_bins-1, bin
+ * width dt > 0 (us), time origin t0_bin (t_n = (n - t0_bin) dt), inclusive fit
+ * range [first, last], and the map row that selects its parameters P^j.
+ * Counts must be finite and >= 0.  They are stored as FP32 when every value
+ * in every fit range is an integer below 2^24 (exact), else as FP64. */
+typedef struct {
+  const double *counts; /* host, n_bins values */
+  int64_t n_bins;
+  double dt;
+  double t0_bin;
+  int64_t first, last;
+  int32_t map_row;
+  int32_t reserved;
+} mu_histo;
+
+/* Check histogram descriptors without a device (same rules as
+ * mu_data_create).  Writes a message into msg (may be NULL). */
+mu_status mu_histo_check(const mu_histo *h, int32_t n_histo, char *msg, int32_t msg_len);
+/* Upload n_histo histograms once; only the fit ranges are copied. */
+mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_histo, mu_data **out);
+mu_status mu_data_destroy(mu_data *data);
+int64_t mu_data_bins(const mu_data *data);     /* total fit-range bins, -1 on NULL */
+int32_t mu_data_histos(const mu_data *data);   /* number of histograms, -1 on NULL */
+int32_t mu_data_is_f64(const mu_data *data);   /* 1 if counts are stored in FP64 */
+
+/* ------------------------------------------------------------------ theory */
+
+typedef enum { MU_SE = 0, MU_GE = 1, MU_SG = 2, MU_STG = 3, MU_TF = 4 } mu_prim;
+/* Primitives and their argument lists (Listing 2, Listing 3):
+ *   MU_SE  (lambda)        exp(-lambda t)
+ *   MU_GE  (lambda, beta)  exp(-(lambda t)^beta)       (t >= 0; beta > 0)
+ *   MU_SG  (sigma)         exp(-(sigma t)^2 / 2)
+ *   MU_STG (sigma)         1/3 + 2/3 (1 - (sigma t)^2) exp(-(sigma t)^2 / 2)
+ *   MU_TF  (phi, nu)       cos(2 pi nu t + phi)                               */
+typedef enum { MU_REF_PAR = 0, MU_REF_FUN = 1, MU_REF_LIT = 2 } mu_ref_kind;
+typedef struct {
+  int32_t kind;    /* mu_ref_kind */
+  int32_t slot;    /* map column for MU_REF_PAR / MU_REF_FUN */
+  double literal;  /* value for MU_REF_LIT */
+} mu_ref;
+typedef struct {
+  int32_t prim;    /* mu_prim */
+  int32_t reserved;
+  mu_ref arg[2];   /* only the first nargs(prim) are read */
+} mu_factor;
+typedef struct {
+  double coef;                 /* literal coefficient */
+  mu_ref amp;                  /* amplitude reference */
+  int32_t first_factor;        /* index into the factor array */
+  int32_t n_factors;           /* 0 .. MU_MAX_FACTORS_PER_TERM */
+} mu_term;
+typedef struct {
+  double tau_mu;               /* muon lifetime in us, > 0 */
+  mu_ref n0, nbkg;             /* N0^j and Nbkg^j */
+  const mu_term *terms;
+  int32_t n_terms;             /* 0 .. MU_MAX_TERMS */
+  const mu_factor *factors;
+  int32_t n_factors;
+  const int32_t *map;          /* [n_rows][n_slots], row-major */
+  int32_t n_rows, n_slots;
+  const double *F;             /* [n_fun][n_par] or NULL when n_fun == 0 */
+  const double *f0;            /* [n_fun] or NULL when n_fun == 0 */
+  int32_t n_fun;
+  int32_t n_par;               /* 1 .. MU_MAX_PAR */
+} mu_theory_desc;
+
+/* Validate a theory without a device.  MU_E_ARG for: n_par outside
+ * [1, MU_MAX_PAR]; tau_mu <= 0 or non-finite; an unknown primitive or
+ * reference kind; a slot outside [0, n_slots); a map entry outside [0, n_par)
+ * for a parameter reference or outside [0, n_fun) for a function reference;
+ * a literal beta <= 0; factor ranges that overlap or leave the array.
+ * MU_E_UNSUPPORTED for more than MU_MAX_TERMS terms or
+ * MU_MAX_FACTORS_PER_TERM factors in a term. */
+mu_status mu_theory_check(const mu_theory_desc *d, char *msg, int32_t msg_len);
+mu_status mu_theory_create(mu_ctx *ctx, const mu_theory_desc *d, mu_theory **out);
+mu_status mu_theory_destroy(mu_theory *th);
+int32_t mu_theory_npar(const mu_theory *th);
+
+/* -------------------------------------------------------------- evaluation */
+
+/* Cost of n_vec parameter vectors (params: [n_vec][n_par] row-major) over
+ * every fit-range bin of every histogram of `data` (Eqs. 2-3), in one launch.
+ * cost: [n_vec].  cost_per_histo: [n_vec][n_histo] or NULL.  Every map row a
+ * histogram names must exist in the theory (else MU_E_ARG).  Non-finite
+ * parameters give a NaN cost; the likelihood with N <= 0 < d gives +inf. */
+mu_status mu_chi2_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                       const double *params, int32_t n_vec, unsigned mem,
+                       double *cost, double *cost_per_histo);
+
+/* Cost and its analytic gradient d cost / d p (adjoint pass: per bin the
+ * cost's derivative in N times dN/dp through Eq. 1, the product form of A and
+ * the map / function array).  grad: [n_vec][n_par]. */
+mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                       const double *params, int32_t n_vec, unsigned mem,
+                       double *cost, double *grad);
+
+/* Batched evaluation of n_jobs independent (dataset, theory, parameter
+ * vector) jobs of uneven sizes in one launch.  params: [n_jobs][ld] with
+ * ld >= every theory's n_par (each job reads its first n_par entries).
+ * cost: [n_jobs]; grad: [n_jobs][ld] or NULL (entries past a job's n_par are
+ * left untouched).  Data and theories may repeat across jobs. */
+mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data,
+                        const mu_theory *const *th, mu_cost cost_kind, int32_t ld,
+                        const double *params, unsigned mem, double *cost, double *grad);
+
+/* Expected counts N(t_n) (Eq. 1) at every fit-range bin of every histogram,
+ * concatenated in histogram order: out[mu_data_bins(data)]. */
+mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
+                        const double *params, unsigned mem, double *out);
+
+/* Tile size (bins per workgroup) used by evaluation launches on this
+ * context: 0 restores the tuned default.  Must be a multiple of 256 in
+ * [256, 65536]; results do not depend on it beyond rounding order. */
+mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins);
+int32_t mu_ctx_get_tile(const mu_ctx *ctx);
+
+/* Lane steps between exact re-evaluations of the theory's factors (the rest
+ * are advanced by exact recurrences of the uniform time grid): 1 evaluates
+ * every bin directly; 0 restores the default (64).  Range [1, 64]; the
+ * recurrence drift stays below ~5e-13 relative at 64. */
+mu_status mu_ctx_set_anchor(mu_ctx *ctx, int32_t every);
+int32_t mu_ctx_get_anchor(const mu_ctx *ctx);
+
+/* 1 (default): theories whose shape matches a compiled specialisation
+ * (A se tf; A sg tf; A stg; A1 se + A2 stg; A1 se tf + A2 stg) run that
+ * kernel; 0: every theory runs the generic interpreted kernel.  Results agree
+ * to rounding either way. */
+mu_status mu_ctx_set_specialize(mu_ctx *ctx, int32_t on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MU_H */

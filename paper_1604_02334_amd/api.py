@@ -1,0 +1,337 @@
+"""Python binding of the C ABI in include/mu.h.
+
+Marshalling only: numpy arrays become host pointers (MU_MEM_HOST), CUDA
+(HIP) torch tensors become device pointers on the context's stream
+(MU_MEM_DEVICE).  Every evaluation runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi as A
+
+
+def _check(status, ctx_handle=None, what=""):
+    if status != A.MU_OK:
+        msg = ""
+        if ctx_handle:
+            raw = A.lib().mu_ctx_last_error(ctx_handle)
+            msg = raw.decode() if raw else ""
+        raise A.MuError(status, f"{what}: {msg or A.lib().mu_status_string(status).decode()}")
+
+
+def _is_torch(x):
+    try:
+        import torch
+        return isinstance(x, torch.Tensor)
+    except ImportError:  # pragma: no cover
+        return False
+
+
+class Context:
+    """A device, a default-priority stream and the library's scratch arena."""
+
+    def __init__(self, device=0):
+        import torch
+        self.device = int(device)
+        self.torch_stream = torch.cuda.Stream(device=self.device)
+        h = C.c_void_p()
+        st = A.lib().mu_ctx_create(self.device, C.c_void_p(self.torch_stream.cuda_stream), 0, C.byref(h))
+        if st != A.MU_OK:
+            raise A.MuError(st, "mu_ctx_create: " + A.lib().mu_status_string(st).decode())
+        self.h = h
+        self._children = []
+
+    def close(self):
+        for c in reversed(self._children):
+            c.close()
+        self._children = []
+        if self.h:
+            _check(A.lib().mu_ctx_destroy(self.h), self.h, "mu_ctx_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def synchronize(self):
+        _check(A.lib().mu_ctx_synchronize(self.h), self.h, "mu_ctx_synchronize")
+
+    @property
+    def tile(self):
+        return A.lib().mu_ctx_get_tile(self.h)
+
+    @tile.setter
+    def tile(self, bins):
+        _check(A.lib().mu_ctx_set_tile(self.h, int(bins)), self.h, "mu_ctx_set_tile")
+
+    @property
+    def anchor(self):
+        return A.lib().mu_ctx_get_anchor(self.h)
+
+    @anchor.setter
+    def anchor(self, every):
+        _check(A.lib().mu_ctx_set_anchor(self.h, int(every)), self.h, "mu_ctx_set_anchor")
+
+    def set_specialize(self, on):
+        _check(A.lib().mu_ctx_set_specialize(self.h, 1 if on else 0), self.h, "mu_ctx_set_specialize")
+
+    # ordering with torch's current stream for device tensors
+    def _enter_device(self):
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        self.torch_stream.wait_stream(cur)
+        return cur
+
+    def _leave_device(self, cur, tensors):
+        cur.wait_stream(self.torch_stream)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.torch_stream)
+
+
+def _ref(r):
+    kind, x = r
+    if kind == "p":
+        return A.mu_ref(A.MU_REF_PAR, int(x), 0.0)
+    if kind == "f":
+        return A.mu_ref(A.MU_REF_FUN, int(x), 0.0)
+    if kind == "lit":
+        return A.mu_ref(A.MU_REF_LIT, 0, float(x))
+    raise ValueError(f"unknown reference kind {kind!r}")
+
+
+def theory_desc(theory):
+    """Build a mu_theory_desc (and the arrays it points to) from a theory dict."""
+    terms = theory["terms"]
+    facs = []
+    tarr = (A.mu_term * max(len(terms), 1))()
+    for k, t in enumerate(terms):
+        tarr[k].coef = float(t["coef"])
+        tarr[k].amp = _ref(t["amp"])
+        tarr[k].first_factor = len(facs)
+        tarr[k].n_factors = len(t["factors"])
+        for f in t["factors"]:
+            mf = A.mu_factor()
+            mf.prim = A.PRIM_CODES.get(f["prim"], 99) if isinstance(f["prim"], str) else int(f["prim"])
+            for a, r in enumerate(f["args"]):
+                mf.arg[a] = _ref(r)
+            facs.append(mf)
+    farr = (A.mu_factor * max(len(facs), 1))(*facs)
+    m = np.ascontiguousarray(np.asarray(theory["map"], dtype=np.int32))
+    if m.ndim != 2:
+        raise ValueError("map must be two-dimensional")
+    F = theory.get("F")
+    keep = [tarr, farr, m]
+    d = A.mu_theory_desc()
+    d.tau_mu = float(theory["tau_mu"])
+    d.n0 = _ref(theory["n0"])
+    d.nbkg = _ref(theory["nbkg"])
+    d.terms = C.cast(tarr, C.POINTER(A.mu_term))
+    d.n_terms = len(terms)
+    d.factors = C.cast(farr, C.POINTER(A.mu_factor))
+    d.n_factors = len(facs)
+    d.map = m.ctypes.data_as(C.POINTER(C.c_int32))
+    d.n_rows, d.n_slots = m.shape
+    if F is not None:
+        Fa = np.ascontiguousarray(np.asarray(F, dtype=np.float64))
+        f0 = np.ascontiguousarray(np.asarray(theory["f0"], dtype=np.float64))
+        keep += [Fa, f0]
+        d.F = Fa.ctypes.data_as(A.dp)
+        d.f0 = f0.ctypes.data_as(A.dp)
+        d.n_fun = Fa.shape[0]
+    else:
+        d.F = None
+        d.f0 = None
+        d.n_fun = 0
+    d.n_par = int(theory["n_par"])
+    return d, keep
+
+
+def theory_check(theory):
+    """Validate a theory dict without a device: (status, message)."""
+    d, keep = theory_desc(theory)
+    buf = C.create_string_buffer(512)
+    st = A.lib().mu_theory_check(C.byref(d), buf, 512)
+    return st, buf.value.decode()
+
+
+def _histo_array(histos, counts):
+    arr = (A.mu_histo * len(histos))()
+    keep = []
+    for j, (h, c) in enumerate(zip(histos, counts)):
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+        keep.append(c)
+        arr[j].counts = c.ctypes.data
+        arr[j].n_bins = int(h["n_bins"])
+        arr[j].dt = float(h["dt"])
+        arr[j].t0_bin = float(h.get("t0_bin", 0.0))
+        arr[j].first = int(h.get("first", 0))
+        arr[j].last = int(h.get("last", h["n_bins"] - 1))
+        arr[j].map_row = int(h.get("map_row", 0))
+    return arr, keep
+
+
+def histo_check(histos, counts):
+    arr, keep = _histo_array(histos, counts)
+    buf = C.create_string_buffer(512)
+    st = A.lib().mu_histo_check(arr, len(histos), buf, 512)
+    return st, buf.value.decode()
+
+
+class Theory:
+    def __init__(self, ctx, theory):
+        d, keep = theory_desc(theory)
+        h = C.c_void_p()
+        _check(A.lib().mu_theory_create(ctx.h, C.byref(d), C.byref(h)), ctx.h, "mu_theory_create")
+        self.h = h
+        self.ctx = ctx
+        self.n_par = int(theory["n_par"])
+        ctx._children.append(self)
+
+    def close(self):
+        if self.h:
+            _check(A.lib().mu_theory_destroy(self.h), None, "mu_theory_destroy")
+            self.h = None
+
+
+class Data:
+    def __init__(self, ctx, histos, counts):
+        arr, keep = _histo_array(histos, counts)
+        h = C.c_void_p()
+        _check(A.lib().mu_data_create(ctx.h, arr, len(histos), C.byref(h)), ctx.h, "mu_data_create")
+        self.h = h
+        self.ctx = ctx
+        self.n_histo = len(histos)
+        self.n_bins = int(A.lib().mu_data_bins(h))
+        self.is_f64 = bool(A.lib().mu_data_is_f64(h))
+        ctx._children.append(self)
+
+    def close(self):
+        if self.h:
+            _check(A.lib().mu_data_destroy(self.h), None, "mu_data_destroy")
+            self.h = None
+
+
+def _cost_code(cost):
+    if cost not in A.COST_CODES:
+        raise ValueError(f"cost must be one of {sorted(A.COST_CODES)}")
+    return A.COST_CODES[cost]
+
+
+def _as_host_params(params, n_par):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    if p.ndim == 1:
+        p = p[None, :]
+    if p.ndim != 2 or p.shape[1] != n_par:
+        raise ValueError(f"params must have shape [n_vec, {n_par}]")
+    return p
+
+
+def chi2_eval(ctx, data, theory, params, cost="chi2", per_histo=False):
+    """Cost of each parameter vector (and optionally of each histogram)."""
+    L = A.lib()
+    if _is_torch(params) and params.is_cuda:
+        import torch
+        p = params.detach().to(torch.float64).contiguous()
+        if p.dim() == 1:
+            p = p[None]
+        n_vec = p.shape[0]
+        out = torch.empty(n_vec, dtype=torch.float64, device=p.device)
+        ph = torch.empty((n_vec, data.n_histo), dtype=torch.float64, device=p.device) if per_histo else None
+        cur = ctx._enter_device()
+        _check(L.mu_chi2_eval(ctx.h, data.h, theory.h, _cost_code(cost), C.c_void_p(p.data_ptr()), n_vec,
+                              A.MU_MEM_DEVICE, C.c_void_p(out.data_ptr()),
+                              C.c_void_p(ph.data_ptr()) if ph is not None else None), ctx.h, "mu_chi2_eval")
+        ctx._leave_device(cur, [p, out, ph])
+        return (out, ph) if per_histo else out
+    p = _as_host_params(params, theory.n_par)
+    n_vec = p.shape[0]
+    out = np.empty(n_vec)
+    ph = np.empty((n_vec, data.n_histo)) if per_histo else None
+    _check(L.mu_chi2_eval(ctx.h, data.h, theory.h, _cost_code(cost), p.ctypes.data, n_vec, A.MU_MEM_HOST,
+                          out.ctypes.data, ph.ctypes.data if ph is not None else None), ctx.h, "mu_chi2_eval")
+    return (out, ph) if per_histo else out
+
+
+def chi2_grad(ctx, data, theory, params, cost="chi2"):
+    """Cost and analytic gradient of each parameter vector."""
+    L = A.lib()
+    if _is_torch(params) and params.is_cuda:
+        import torch
+        p = params.detach().to(torch.float64).contiguous()
+        if p.dim() == 1:
+            p = p[None]
+        n_vec = p.shape[0]
+        out = torch.empty(n_vec, dtype=torch.float64, device=p.device)
+        g = torch.empty((n_vec, theory.n_par), dtype=torch.float64, device=p.device)
+        cur = ctx._enter_device()
+        _check(L.mu_chi2_grad(ctx.h, data.h, theory.h, _cost_code(cost), C.c_void_p(p.data_ptr()), n_vec,
+                              A.MU_MEM_DEVICE, C.c_void_p(out.data_ptr()), C.c_void_p(g.data_ptr())),
+               ctx.h, "mu_chi2_grad")
+        ctx._leave_device(cur, [p, out, g])
+        return out, g
+    p = _as_host_params(params, theory.n_par)
+    n_vec = p.shape[0]
+    out = np.empty(n_vec)
+    g = np.empty((n_vec, theory.n_par))
+    _check(L.mu_chi2_grad(ctx.h, data.h, theory.h, _cost_code(cost), p.ctypes.data, n_vec, A.MU_MEM_HOST,
+                          out.ctypes.data, g.ctypes.data), ctx.h, "mu_chi2_grad")
+    return out, g
+
+
+def chi2_batch(ctx, datas, theories, params, cost="chi2", grad=False):
+    """One launch over independent (dataset, theory, vector) jobs.
+    params: [n_jobs, ld] with ld >= every theory's n_par."""
+    L = A.lib()
+    n = len(datas)
+    if len(theories) != n:
+        raise ValueError("need one theory per dataset")
+    dh = (C.c_void_p * n)(*[d.h.value for d in datas])
+    th = (C.c_void_p * n)(*[t.h.value for t in theories])
+    if _is_torch(params) and params.is_cuda:
+        import torch
+        p = params.detach().to(torch.float64).contiguous()
+        ld = p.shape[1]
+        out = torch.empty(n, dtype=torch.float64, device=p.device)
+        g = torch.zeros((n, ld), dtype=torch.float64, device=p.device) if grad else None
+        cur = ctx._enter_device()
+        _check(L.mu_chi2_batch(ctx.h, n, dh, th, _cost_code(cost), ld, C.c_void_p(p.data_ptr()), A.MU_MEM_DEVICE,
+                               C.c_void_p(out.data_ptr()), C.c_void_p(g.data_ptr()) if grad else None),
+               ctx.h, "mu_chi2_batch")
+        ctx._leave_device(cur, [p, out, g])
+        return (out, g) if grad else out
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    if p.ndim != 2 or p.shape[0] != n:
+        raise ValueError("params must have shape [n_jobs, ld]")
+    ld = p.shape[1]
+    out = np.empty(n)
+    g = np.zeros((n, ld)) if grad else None
+    _check(L.mu_chi2_batch(ctx.h, n, dh, th, _cost_code(cost), ld, p.ctypes.data, A.MU_MEM_HOST, out.ctypes.data,
+                           g.ctypes.data if grad else None), ctx.h, "mu_chi2_batch")
+    return (out, g) if grad else out
+
+
+def model_eval(ctx, data, theory, params):
+    """Expected counts N (Eq. 1) at every fit-range bin, histograms concatenated."""
+    L = A.lib()
+    if _is_torch(params) and params.is_cuda:
+        import torch
+        p = params.detach().to(torch.float64).contiguous().reshape(-1)
+        out = torch.empty(data.n_bins, dtype=torch.float64, device=p.device)
+        cur = ctx._enter_device()
+        _check(L.mu_model_eval(ctx.h, data.h, theory.h, C.c_void_p(p.data_ptr()), A.MU_MEM_DEVICE,
+                               C.c_void_p(out.data_ptr())), ctx.h, "mu_model_eval")
+        ctx._leave_device(cur, [p, out])
+        return out
+    p = _as_host_params(params, theory.n_par)[0]
+    p = np.ascontiguousarray(p)
+    out = np.empty(data.n_bins)
+    _check(L.mu_model_eval(ctx.h, data.h, theory.h, p.ctypes.data, A.MU_MEM_HOST, out.ctypes.data), ctx.h,
+           "mu_model_eval")
+    return out

@@ -1,0 +1,988 @@
+// Host runtime of the C ABI declared in include/mu.h: contexts, device-resident
+// histograms, validated theory programs and evaluation launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mu_internal.h"
+#include "mu_runtime.h"
+
+using namespace mu;
+
+// ------------------------------------------------------------------ helpers
+
+namespace mu {
+
+void set_err(mu_ctx *ctx, const char *fmt, ...) {
+  if (!ctx) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  ctx->err = buf;
+}
+
+static void put_msg(char *msg, int32_t len, const std::string &s) {
+  if (msg && len > 0) {
+    std::snprintf(msg, (size_t)len, "%s", s.c_str());
+  }
+}
+
+mu_status hip_fail(mu_ctx *ctx, hipError_t e, const char *what) {
+  set_err(ctx, "%s failed: %s", what, hipGetErrorString(e));
+  return MU_E_DEVICE;
+}
+
+mu_status DevBuf::ensure(mu_ctx *ctx, size_t bytes, bool zero) {
+  if (bytes <= cap) return MU_OK;
+  if (ptr) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  want = (want + 4095) & ~size_t(4095);
+  hipError_t e = hipMalloc(&ptr, want);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    set_err(ctx, "device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+    return MU_E_NOMEM;
+  }
+  cap = want;
+  if (zero) {
+    e = hipMemsetAsync(ptr, 0, want, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync");
+  }
+  return MU_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+mu_status HostBuf::ensure(mu_ctx *ctx, size_t bytes) {
+  if (bytes <= cap) return MU_OK;
+  if (ptr) {
+    hipStreamSynchronize(ctx->stream);
+    hipHostFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  want = (want + 4095) & ~size_t(4095);
+  hipError_t e = hipHostMalloc(&ptr, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    set_err(ctx, "pinned host allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+    return MU_E_NOMEM;
+  }
+  cap = want;
+  return MU_OK;
+}
+
+void HostBuf::release() {
+  if (ptr) hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+}  // namespace mu
+
+// ----------------------------------------------------------------- version
+
+extern "C" int mu_abi_version(void) { return MU_ABI_VERSION; }
+
+extern "C" const char *mu_status_string(mu_status s) {
+  switch (s) {
+    case MU_OK: return "ok";
+    case MU_E_ARG: return "invalid argument";
+    case MU_E_NODEVICE: return "no usable GPU";
+    case MU_E_NOMEM: return "out of memory";
+    case MU_E_DEVICE: return "HIP error";
+    case MU_E_UNSUPPORTED: return "unsupported";
+    case MU_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+// ----------------------------------------------------------------- context
+
+static bool forced_nodevice() {
+  const char *v = std::getenv("MU_FORCE_NODEVICE");
+  return v && v[0] && std::strcmp(v, "0") != 0;
+}
+
+extern "C" mu_status mu_ctx_create(int device, void *hip_stream, unsigned flags, mu_ctx **out) {
+  if (!out) return MU_E_ARG;
+  *out = nullptr;
+  if (flags != 0) return MU_E_ARG;
+  if (forced_nodevice()) return MU_E_NODEVICE;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MU_E_NODEVICE;
+  if (device < 0 || device >= n) return MU_E_ARG;
+  if (hipSetDevice(device) != hipSuccess) return MU_E_NODEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MU_E_DEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MU_E_UNSUPPORTED;
+  mu_ctx *c = new mu_ctx();
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->own_stream = false;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return MU_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  if (hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming) != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return MU_E_DEVICE;
+  }
+  *out = c;
+  return MU_OK;
+}
+
+extern "C" mu_status mu_ctx_destroy(mu_ctx *ctx) {
+  if (!ctx) return MU_E_ARG;
+  if (ctx->children != 0) {
+    set_err(ctx, "context still owns %d live handles", ctx->children);
+    return MU_E_STATE;
+  }
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  ctx->release_all();
+  if (ctx->staging_free) hipEventDestroy(ctx->staging_free);
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return MU_OK;
+}
+
+void mu_ctx::release_all() {
+  partial.release();
+  dparams.release();
+  dout.release();
+  djobs.release();
+  staging.release();
+  staging_out.release();
+  for (auto &b : extra) b.release();
+}
+
+extern "C" const char *mu_ctx_last_error(const mu_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" mu_status mu_ctx_synchronize(mu_ctx *ctx) {
+  if (!ctx) return MU_E_ARG;
+  hipSetDevice(ctx->device);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "hipStreamSynchronize");
+}
+
+extern "C" mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins) {
+  if (!ctx) return MU_E_ARG;
+  if (tile_bins == 0) {
+    ctx->tile_bins = kDefaultTile;
+    return MU_OK;
+  }
+  if (tile_bins < kBlock || tile_bins > 65536 || tile_bins % kBlock) {
+    set_err(ctx, "tile_bins must be a multiple of %d in [%d, 65536]", kBlock, kBlock);
+    return MU_E_ARG;
+  }
+  ctx->tile_bins = tile_bins;
+  return MU_OK;
+}
+
+extern "C" int32_t mu_ctx_get_tile(const mu_ctx *ctx) { return ctx ? ctx->tile_bins : -1; }
+
+extern "C" mu_status mu_ctx_set_anchor(mu_ctx *ctx, int32_t every) {
+  if (!ctx) return MU_E_ARG;
+  if (every == 0) {
+    ctx->anchor_every = kDefaultAnchor;
+    return MU_OK;
+  }
+  if (every < 1 || every > 64) {
+    set_err(ctx, "anchor interval must be in [1, 64] lane steps");
+    return MU_E_ARG;
+  }
+  ctx->anchor_every = every;
+  return MU_OK;
+}
+
+extern "C" int32_t mu_ctx_get_anchor(const mu_ctx *ctx) { return ctx ? ctx->anchor_every : -1; }
+
+extern "C" mu_status mu_ctx_set_specialize(mu_ctx *ctx, int32_t on) {
+  if (!ctx || (on != 0 && on != 1)) return MU_E_ARG;
+  ctx->specialize = on;
+  return MU_OK;
+}
+
+// -------------------------------------------------------------- histograms
+
+static mu_status check_histos(const mu_histo *h, int32_t n, std::string &why, bool *all_int) {
+  if (!h || n <= 0) {
+    why = "need at least one histogram";
+    return MU_E_ARG;
+  }
+  bool ints = true;
+  for (int32_t j = 0; j < n; ++j) {
+    const mu_histo &x = h[j];
+    char b[256];
+    if (!x.counts) {
+      std::snprintf(b, sizeof b, "histogram %d: counts is NULL", j);
+      why = b;
+      return MU_E_ARG;
+    }
+    if (x.n_bins <= 0 || !(x.dt > 0.0) || !std::isfinite(x.dt) || !std::isfinite(x.t0_bin)) {
+      std::snprintf(b, sizeof b, "histogram %d: need n_bins > 0, finite dt > 0 and finite t0_bin", j);
+      why = b;
+      return MU_E_ARG;
+    }
+    if (x.first < 0 || x.last < x.first || x.last >= x.n_bins) {
+      std::snprintf(b, sizeof b, "histogram %d: fit range [%lld, %lld] outside [0, %lld)", j, (long long)x.first,
+                    (long long)x.last, (long long)x.n_bins);
+      why = b;
+      return MU_E_ARG;
+    }
+    if (x.map_row < 0) {
+      std::snprintf(b, sizeof b, "histogram %d: negative map row", j);
+      why = b;
+      return MU_E_ARG;
+    }
+    if (x.last - x.first + 1 > (int64_t)1 << 40) {
+      std::snprintf(b, sizeof b, "histogram %d: fit range too long", j);
+      why = b;
+      return MU_E_UNSUPPORTED;
+    }
+    for (int64_t n2 = x.first; n2 <= x.last; ++n2) {
+      const double d = x.counts[n2];
+      if (!std::isfinite(d) || d < 0.0) {
+        std::snprintf(b, sizeof b, "histogram %d: count %lld is negative or non-finite", j, (long long)n2);
+        why = b;
+        return MU_E_ARG;
+      }
+      if (ints && (d != std::floor(d) || d >= 16777216.0)) ints = false;
+    }
+  }
+  if (all_int) *all_int = ints;
+  return MU_OK;
+}
+
+extern "C" mu_status mu_histo_check(const mu_histo *h, int32_t n_histo, char *msg, int32_t msg_len) {
+  std::string why;
+  mu_status s = check_histos(h, n_histo, why, nullptr);
+  put_msg(msg, msg_len, s == MU_OK ? std::string("ok") : why);
+  return s;
+}
+
+mu_status mu_data::build_tiles(int tile_bins) {
+  if (tile_bins == tiles_for) return MU_OK;
+  std::vector<DevTile> tl;
+  for (int j = 0; j < n_histo; ++j) {
+    hh[j].tile0 = (int32_t)tl.size();
+    for (int64_t b = 0; b < hh[j].n; b += tile_bins) {
+      DevTile t;
+      t.begin = b;
+      t.histo = j;
+      t.n = (int32_t)std::min<int64_t>(tile_bins, hh[j].n - b);
+      tl.push_back(t);
+    }
+  }
+  if (tl.size() > (size_t)INT32_MAX / 2) {
+    set_err(ctx, "dataset needs too many tiles");
+    return MU_E_UNSUPPORTED;
+  }
+  hipStreamSynchronize(ctx->stream);  // earlier launches may still read the old tables
+  if (d_tiles) hipFree(d_tiles);
+  d_tiles = nullptr;
+  hipError_t e = hipMalloc(&d_tiles, tl.size() * sizeof(DevTile));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(tiles)");
+  e = hipMemcpy(d_tiles, tl.data(), tl.size() * sizeof(DevTile), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(tiles)");
+  e = hipMemcpy(d_histos, hh.data(), hh.size() * sizeof(DevHisto), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(histos)");
+  n_tiles = (int32_t)tl.size();
+  tiles_for = tile_bins;
+  return MU_OK;
+}
+
+extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_histo, mu_data **out) {
+  if (!ctx || !out) return MU_E_ARG;
+  *out = nullptr;
+  std::string why;
+  bool ints = false;
+  mu_status st = check_histos(h, n_histo, why, &ints);
+  if (st != MU_OK) {
+    set_err(ctx, "%s", why.c_str());
+    return st;
+  }
+  hipSetDevice(ctx->device);
+  mu_data *d = new mu_data();
+  d->ctx = ctx;
+  d->n_histo = n_histo;
+  d->f64 = ints ? 0 : 1;
+  int64_t total = 0;
+  d->hh.resize(n_histo);
+  for (int j = 0; j < n_histo; ++j) {
+    DevHisto &x = d->hh[j];
+    x.off = total;
+    x.n = h[j].last - h[j].first + 1;
+    x.first = h[j].first;
+    x.t0_bin = h[j].t0_bin;
+    x.dt = h[j].dt;
+    x.map_row = h[j].map_row;
+    x.tile0 = 0;
+    d->max_row = std::max(d->max_row, (int)h[j].map_row);
+    total += x.n;
+  }
+  d->total = total;
+  const size_t esz = d->f64 ? sizeof(double) : sizeof(float);
+  hipError_t e = hipMalloc(&d->counts, (size_t)total * esz);
+  if (e != hipSuccess) {
+    delete d;
+    set_err(ctx, "device allocation for %lld bins failed", (long long)total);
+    return MU_E_NOMEM;
+  }
+  e = hipMalloc(&d->d_histos, n_histo * sizeof(DevHisto));
+  if (e != hipSuccess) {
+    hipFree(d->counts);
+    delete d;
+    return MU_E_NOMEM;
+  }
+  // pack on the host, upload once
+  {
+    std::vector<char> buf((size_t)total * esz);
+    for (int j = 0; j < n_histo; ++j) {
+      const DevHisto &x = d->hh[j];
+      for (int64_t i = 0; i < x.n; ++i) {
+        const double v = h[j].counts[x.first + i];
+        if (d->f64)
+          reinterpret_cast<double *>(buf.data())[x.off + i] = v;
+        else
+          reinterpret_cast<float *>(buf.data())[x.off + i] = (float)v;
+      }
+    }
+    e = hipMemcpy(d->counts, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    hipFree(d->counts);
+    hipFree(d->d_histos);
+    delete d;
+    return hip_fail(ctx, e, "hipMemcpy(counts)");
+  }
+  st = d->build_tiles(ctx->tile_bins);
+  if (st != MU_OK) {
+    hipFree(d->counts);
+    hipFree(d->d_histos);
+    if (d->d_tiles) hipFree(d->d_tiles);
+    delete d;
+    return st;
+  }
+  ctx->children++;
+  *out = d;
+  return MU_OK;
+}
+
+extern "C" mu_status mu_data_destroy(mu_data *d) {
+  if (!d) return MU_E_ARG;
+  hipSetDevice(d->ctx->device);
+  hipStreamSynchronize(d->ctx->stream);
+  hipFree(d->counts);
+  hipFree(d->d_histos);
+  if (d->d_tiles) hipFree(d->d_tiles);
+  d->ctx->children--;
+  delete d;
+  return MU_OK;
+}
+
+extern "C" int64_t mu_data_bins(const mu_data *d) { return d ? d->total : -1; }
+extern "C" int32_t mu_data_histos(const mu_data *d) { return d ? d->n_histo : -1; }
+extern "C" int32_t mu_data_is_f64(const mu_data *d) { return d ? d->f64 : -1; }
+
+// ------------------------------------------------------------------ theory
+
+static int prim_nargs(int p) {
+  switch (p) {
+    case MU_SE: return 1;
+    case MU_GE: return 2;
+    case MU_SG: return 1;
+    case MU_STG: return 1;
+    case MU_TF: return 2;
+  }
+  return -1;
+}
+
+static mu_status check_ref(const mu_theory_desc *d, const mu_ref &r, const char *what, std::string &why) {
+  char b[256];
+  if (r.kind == MU_REF_LIT) {
+    if (!std::isfinite(r.literal)) {
+      std::snprintf(b, sizeof b, "%s: literal is not finite", what);
+      why = b;
+      return MU_E_ARG;
+    }
+    return MU_OK;
+  }
+  if (r.kind != MU_REF_PAR && r.kind != MU_REF_FUN) {
+    std::snprintf(b, sizeof b, "%s: unknown reference kind %d", what, r.kind);
+    why = b;
+    return MU_E_ARG;
+  }
+  if (r.slot < 0 || r.slot >= d->n_slots) {
+    std::snprintf(b, sizeof b, "%s: slot %d outside [0, %d)", what, r.slot, d->n_slots);
+    why = b;
+    return MU_E_ARG;
+  }
+  const int lim = r.kind == MU_REF_PAR ? d->n_par : d->n_fun;
+  for (int row = 0; row < d->n_rows; ++row) {
+    const int v = d->map[row * d->n_slots + r.slot];
+    if (v < 0 || v >= lim) {
+      std::snprintf(b, sizeof b, "%s: map[%d][%d] = %d outside [0, %d) for a %s reference", what, row, r.slot, v, lim,
+                    r.kind == MU_REF_PAR ? "parameter" : "function");
+      why = b;
+      return MU_E_ARG;
+    }
+  }
+  return MU_OK;
+}
+
+static mu_status check_theory(const mu_theory_desc *d, std::string &why) {
+  if (!d) {
+    why = "null theory";
+    return MU_E_ARG;
+  }
+  if (d->n_par < 1 || d->n_par > MU_MAX_PAR) {
+    why = "n_par outside [1, MU_MAX_PAR]";
+    return MU_E_ARG;
+  }
+  if (!(d->tau_mu > 0.0) || !std::isfinite(d->tau_mu)) {
+    why = "tau_mu must be finite and > 0";
+    return MU_E_ARG;
+  }
+  if (d->n_rows < 1 || d->n_slots < 1 || !d->map) {
+    why = "the map needs at least one row and one slot";
+    return MU_E_ARG;
+  }
+  if (d->n_fun < 0 || (d->n_fun > 0 && (!d->F || !d->f0))) {
+    why = "n_fun > 0 needs F and f0";
+    return MU_E_ARG;
+  }
+  if (d->n_fun > 0) {
+    for (int64_t i = 0; i < (int64_t)d->n_fun * d->n_par; ++i)
+      if (!std::isfinite(d->F[i])) {
+        why = "F holds a non-finite value";
+        return MU_E_ARG;
+      }
+    for (int i = 0; i < d->n_fun; ++i)
+      if (!std::isfinite(d->f0[i])) {
+        why = "f0 holds a non-finite value";
+        return MU_E_ARG;
+      }
+  }
+  if (d->n_terms < 0 || (d->n_terms > 0 && !d->terms)) {
+    why = "bad term array";
+    return MU_E_ARG;
+  }
+  if (d->n_terms > MU_MAX_TERMS) {
+    why = "more than MU_MAX_TERMS terms";
+    return MU_E_UNSUPPORTED;
+  }
+  if (d->n_factors < 0 || (d->n_factors > 0 && !d->factors)) {
+    why = "bad factor array";
+    return MU_E_ARG;
+  }
+  mu_status s;
+  if ((s = check_ref(d, d->n0, "N0", why)) != MU_OK) return s;
+  if ((s = check_ref(d, d->nbkg, "Nbkg", why)) != MU_OK) return s;
+  std::vector<int> used(d->n_factors, 0);
+  for (int k = 0; k < d->n_terms; ++k) {
+    const mu_term &t = d->terms[k];
+    char what[64];
+    std::snprintf(what, sizeof what, "term %d amplitude", k);
+    if (!std::isfinite(t.coef)) {
+      why = "term coefficient is not finite";
+      return MU_E_ARG;
+    }
+    if ((s = check_ref(d, t.amp, what, why)) != MU_OK) return s;
+    if (t.n_factors < 0 || t.first_factor < 0 || t.first_factor + t.n_factors > d->n_factors) {
+      why = "term factor range leaves the factor array";
+      return MU_E_ARG;
+    }
+    if (t.n_factors > MU_MAX_FACTORS_PER_TERM) {
+      why = "more than MU_MAX_FACTORS_PER_TERM factors in a term";
+      return MU_E_UNSUPPORTED;
+    }
+    for (int i = 0; i < t.n_factors; ++i) {
+      const int fi = t.first_factor + i;
+      if (used[fi]++) {
+        why = "factor ranges of two terms overlap";
+        return MU_E_ARG;
+      }
+      const mu_factor &f = d->factors[fi];
+      const int na = prim_nargs(f.prim);
+      if (na < 0) {
+        char b[64];
+        std::snprintf(b, sizeof b, "factor %d: unknown primitive %d", fi, f.prim);
+        why = b;
+        return MU_E_ARG;
+      }
+      for (int a = 0; a < na; ++a) {
+        std::snprintf(what, sizeof what, "factor %d argument %d", fi, a);
+        if ((s = check_ref(d, f.arg[a], what, why)) != MU_OK) return s;
+      }
+      if (f.prim == MU_GE && f.arg[1].kind == MU_REF_LIT && !(f.arg[1].literal > 0.0)) {
+        why = "a literal beta of ge must be > 0";
+        return MU_E_ARG;
+      }
+    }
+  }
+  return MU_OK;
+}
+
+// The compiled specialisation that matches a theory program, if any.
+static int detect_shape(const DevTheory &h) {
+  if (h.n_terms == 1 && h.nf[0] == 2 && h.prim[0][0] == MU_SE && h.prim[0][1] == MU_TF) return kShapeExpCos;
+  if (h.n_terms == 1 && h.nf[0] == 2 && h.prim[0][0] == MU_SG && h.prim[0][1] == MU_TF) return kShapeGaussCos;
+  if (h.n_terms == 1 && h.nf[0] == 1 && h.prim[0][0] == MU_STG) return kShapeStg;
+  if (h.n_terms == 2 && h.nf[0] == 1 && h.prim[0][0] == MU_SE && h.nf[1] == 1 && h.prim[1][0] == MU_STG)
+    return kShapeExpStg;
+  if (h.n_terms == 2 && h.nf[0] == 2 && h.prim[0][0] == MU_SE && h.prim[0][1] == MU_TF && h.nf[1] == 1 &&
+      h.prim[1][0] == MU_STG)
+    return kShapeExpCosStg;
+  return kShapeGeneric;
+}
+
+extern "C" mu_status mu_theory_check(const mu_theory_desc *d, char *msg, int32_t msg_len) {
+  std::string why;
+  mu_status s = check_theory(d, why);
+  put_msg(msg, msg_len, s == MU_OK ? std::string("ok") : why);
+  return s;
+}
+
+extern "C" mu_status mu_theory_create(mu_ctx *ctx, const mu_theory_desc *d, mu_theory **out) {
+  if (!ctx || !out) return MU_E_ARG;
+  *out = nullptr;
+  std::string why;
+  mu_status s = check_theory(d, why);
+  if (s != MU_OK) {
+    set_err(ctx, "%s", why.c_str());
+    return s;
+  }
+  hipSetDevice(ctx->device);
+  mu_theory *th = new mu_theory();
+  th->ctx = ctx;
+  DevTheory &h = th->h;
+  std::memset(&h, 0, sizeof h);
+  h.tau_mu = d->tau_mu;
+  h.neg_inv_tau = -1.0 / d->tau_mu;
+  h.n_terms = d->n_terms;
+  h.n_par = d->n_par;
+  h.n_fun = d->n_fun;
+  h.n_rows = d->n_rows;
+  h.n_slots = d->n_slots;
+  for (int r = 0; r < kRS; ++r) h.rref[r].kind = kRefNone;
+  auto put = [&](int r, const mu_ref &x) {
+    h.rref[r].kind = x.kind;
+    h.rref[r].slot = x.slot;
+    h.rref[r].lit = x.literal;
+  };
+  put(0, d->n0);
+  put(1, d->nbkg);
+  for (int k = 0; k < d->n_terms; ++k) {
+    const mu_term &t = d->terms[k];
+    h.coef[k] = t.coef;
+    h.nf[k] = t.n_factors;
+    put(2 + k, t.amp);
+    for (int i = 0; i < t.n_factors; ++i) {
+      const mu_factor &f = d->factors[t.first_factor + i];
+      h.prim[k][i] = f.prim;
+      const int na = prim_nargs(f.prim);
+      for (int a = 0; a < na; ++a) put(arg_index(k, i, a), f.arg[a]);
+      // an unused second argument resolves to the literal 0
+      if (na < 2) {
+        h.rref[arg_index(k, i, 1)].kind = MU_REF_LIT;
+        h.rref[arg_index(k, i, 1)].lit = 0.0;
+      }
+    }
+  }
+  th->shape = detect_shape(h);
+  th->map.assign(d->map, d->map + (size_t)d->n_rows * d->n_slots);
+  if (d->n_fun > 0) {
+    th->F.assign(d->F, d->F + (size_t)d->n_fun * d->n_par);
+    th->f0.assign(d->f0, d->f0 + d->n_fun);
+  }
+  hipError_t e = hipSuccess;
+  auto up = [&](void **dst, const void *src, size_t n) {
+    if (e != hipSuccess || n == 0) return;
+    e = hipMalloc(dst, n);
+    if (e == hipSuccess) e = hipMemcpy(*dst, src, n, hipMemcpyHostToDevice);
+  };
+  up((void **)&th->d_map, th->map.data(), th->map.size() * sizeof(int32_t));
+  up((void **)&th->d_F, th->F.data(), th->F.size() * sizeof(double));
+  up((void **)&th->d_f0, th->f0.data(), th->f0.size() * sizeof(double));
+  h.map = th->d_map;
+  h.F = th->d_F;
+  h.f0 = th->d_f0;
+  up((void **)&th->d_th, &h, sizeof h);
+  if (e != hipSuccess) {
+    th->free_dev();
+    delete th;
+    return hip_fail(ctx, e, "theory upload");
+  }
+  ctx->children++;
+  *out = th;
+  return MU_OK;
+}
+
+void mu_theory::free_dev() {
+  if (d_map) hipFree(d_map);
+  if (d_F) hipFree(d_F);
+  if (d_f0) hipFree(d_f0);
+  if (d_th) hipFree(d_th);
+  d_map = nullptr;
+  d_F = d_f0 = nullptr;
+  d_th = nullptr;
+}
+
+extern "C" mu_status mu_theory_destroy(mu_theory *th) {
+  if (!th) return MU_E_ARG;
+  hipSetDevice(th->ctx->device);
+  hipStreamSynchronize(th->ctx->stream);
+  th->free_dev();
+  th->ctx->children--;
+  delete th;
+  return MU_OK;
+}
+
+extern "C" int32_t mu_theory_npar(const mu_theory *th) { return th ? th->h.n_par : -1; }
+
+// -------------------------------------------------------------- evaluation
+
+namespace mu {
+
+// Common argument checks for one (data, theory) pair.
+mu_status check_pair(mu_ctx *ctx, const mu_data *d, const mu_theory *th) {
+  if (!d || !th) {
+    set_err(ctx, "null data or theory handle");
+    return MU_E_ARG;
+  }
+  if (d->ctx != ctx || th->ctx != ctx) {
+    set_err(ctx, "data and theory must belong to this context");
+    return MU_E_ARG;
+  }
+  if (d->max_row >= th->h.n_rows) {
+    set_err(ctx, "a histogram names map row %d but the theory has %d rows", d->max_row, th->h.n_rows);
+    return MU_E_ARG;
+  }
+  return MU_OK;
+}
+
+}  // namespace mu
+
+namespace {
+
+// Evaluate n_vec vectors over one dataset in one launch.  mode: cost, grad, model.
+mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *params,
+                       int32_t n_vec, unsigned mem, double *cost, double *histo, double *grad, double *model,
+                       int mode) {
+  if (mem != MU_MEM_HOST && mem != MU_MEM_DEVICE) {
+    set_err(ctx, "mem must be MU_MEM_HOST or MU_MEM_DEVICE");
+    return MU_E_ARG;
+  }
+  if (cost_kind != MU_COST_CHI2 && cost_kind != MU_COST_POISSON) {
+    set_err(ctx, "unknown cost kind %d", cost_kind);
+    return MU_E_ARG;
+  }
+  if (n_vec < 1 || !params) {
+    set_err(ctx, "need n_vec >= 1 and a parameter array");
+    return MU_E_ARG;
+  }
+  mu_status st;
+  hipSetDevice(ctx->device);
+  if ((st = d->build_tiles(ctx->tile_bins)) != MU_OK) return st;
+  const int n_par = th->h.n_par;
+  const int64_t n_blocks = (int64_t)n_vec * d->n_tiles;
+  if (n_blocks > INT32_MAX) {
+    set_err(ctx, "launch needs more than 2^31 workgroups");
+    return MU_E_UNSUPPORTED;
+  }
+  const size_t n_p = (size_t)n_vec * n_par;
+  const size_t n_h = histo ? (size_t)n_vec * d->n_histo : 0;
+  const size_t n_g = grad ? (size_t)n_vec * n_par : 0;
+  const size_t n_c = mode == kModeModel ? 0 : (size_t)n_vec;
+  const size_t n_m = mode == kModeModel ? (size_t)d->total : 0;
+  const double *dp = params;
+  double *dc = cost, *dh = histo, *dg = grad, *dm = model;
+  hipError_t e;
+  if (mem == MU_MEM_HOST) {
+    if ((st = ctx->dparams.ensure(ctx, n_p * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->dout.ensure(ctx, (n_c + n_h + n_g + n_m) * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->staging.ensure(ctx, n_p * sizeof(double))) != MU_OK) return st;
+    if ((st = ctx->staging_out.ensure(ctx, (n_c + n_h + n_g + n_m) * sizeof(double))) != MU_OK) return st;
+    ctx->wait_staging();
+    std::memcpy(ctx->staging.ptr, params, n_p * sizeof(double));
+    e = hipMemcpyAsync(ctx->dparams.ptr, ctx->staging.ptr, n_p * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(params)");
+    ctx->mark_staging();
+    dp = static_cast<double *>(ctx->dparams.ptr);
+    double *o = static_cast<double *>(ctx->dout.ptr);
+    dc = n_c ? o : nullptr;
+    dh = n_h ? o + n_c : nullptr;
+    dg = n_g ? o + n_c + n_h : nullptr;
+    dm = n_m ? o + n_c + n_h + n_g : nullptr;
+  }
+  if (mode != kModeModel) {
+    if ((st = ctx->partial.ensure(ctx, (size_t)n_blocks * kSlot * sizeof(double), false)) != MU_OK) return st;
+  }
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.tmpl.th = th->d_th;
+  a.tmpl.histos = d->d_histos;
+  a.tmpl.counts = d->counts;
+  a.tmpl.tiles = d->d_tiles;
+  a.tmpl.p = dp;
+  a.tmpl.cost_out = dc;
+  a.tmpl.histo_out = dh;
+  a.tmpl.grad_out = dg;
+  a.tmpl.model_out = dm;
+  a.tmpl.n_tiles = d->n_tiles;
+  a.tmpl.n_histo = d->n_histo;
+  a.p_stride = n_par;
+  a.grad_stride = n_par;
+  a.histo_stride = d->n_histo;
+  a.jobs = nullptr;
+  a.block_job = nullptr;
+  a.n_blocks = (int32_t)n_blocks;
+  a.cost_kind = cost_kind;
+  a.anchor_every = ctx->anchor_every;
+  a.partial = static_cast<double *>(ctx->partial.ptr);
+  e = launch_eval(a, mode, d->f64, ctx->specialize ? th->shape : kShapeGeneric, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
+  if (mode != kModeModel) {
+    e = launch_merge(a, mode, n_vec, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
+  }
+  if (mem == MU_MEM_HOST) {
+    const size_t n_out = n_c + n_h + n_g + n_m;
+    e = hipMemcpyAsync(ctx->staging_out.ptr, ctx->dout.ptr, n_out * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(results)");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    const double *o = static_cast<const double *>(ctx->staging_out.ptr);
+    if (n_c) std::memcpy(cost, o, n_c * sizeof(double));
+    if (n_h) std::memcpy(histo, o + n_c, n_h * sizeof(double));
+    if (n_g) std::memcpy(grad, o + n_c + n_h, n_g * sizeof(double));
+    if (n_m) std::memcpy(model, o + n_c + n_h + n_g, n_m * sizeof(double));
+  }
+  return MU_OK;
+}
+
+}  // namespace
+
+extern "C" mu_status mu_chi2_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                                  const double *params, int32_t n_vec, unsigned mem, double *cost,
+                                  double *cost_per_histo) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (!cost) {
+    set_err(ctx, "cost output is NULL");
+    return MU_E_ARG;
+  }
+  return eval_uniform(ctx, const_cast<mu_data *>(data), th, cost_kind, params, n_vec, mem, cost, cost_per_histo,
+                      nullptr, nullptr, kModeCost);
+}
+
+extern "C" mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                                  const double *params, int32_t n_vec, unsigned mem, double *cost, double *grad) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (!cost || !grad) {
+    set_err(ctx, "cost and grad outputs must not be NULL");
+    return MU_E_ARG;
+  }
+  return eval_uniform(ctx, const_cast<mu_data *>(data), th, cost_kind, params, n_vec, mem, cost, nullptr, grad,
+                      nullptr, kModeGrad);
+}
+
+extern "C" mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th, const double *params,
+                                   unsigned mem, double *out) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (!out) {
+    set_err(ctx, "output is NULL");
+    return MU_E_ARG;
+  }
+  return eval_uniform(ctx, const_cast<mu_data *>(data), th, MU_COST_CHI2, params, 1, mem, nullptr, nullptr, nullptr,
+                      out, kModeModel);
+}
+
+extern "C" mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data,
+                                   const mu_theory *const *th, mu_cost cost_kind, int32_t ld, const double *params,
+                                   unsigned mem, double *cost, double *grad) {
+  if (!ctx) return MU_E_ARG;
+  if (n_jobs < 1 || !data || !th || !params || !cost || ld < 1) {
+    set_err(ctx, "need n_jobs >= 1, ld >= 1 and non-NULL data, theory, params and cost");
+    return MU_E_ARG;
+  }
+  if (mem != MU_MEM_HOST && mem != MU_MEM_DEVICE) {
+    set_err(ctx, "mem must be MU_MEM_HOST or MU_MEM_DEVICE");
+    return MU_E_ARG;
+  }
+  if (cost_kind != MU_COST_CHI2 && cost_kind != MU_COST_POISSON) {
+    set_err(ctx, "unknown cost kind %d", cost_kind);
+    return MU_E_ARG;
+  }
+  mu_status st;
+  int f64 = -1;
+  for (int j = 0; j < n_jobs; ++j) {
+    if ((st = check_pair(ctx, data[j], th[j])) != MU_OK) return st;
+    if (th[j]->h.n_par > ld) {
+      set_err(ctx, "job %d: theory has %d parameters but ld is %d", j, th[j]->h.n_par, ld);
+      return MU_E_ARG;
+    }
+    if (f64 < 0) f64 = data[j]->f64;
+    if (data[j]->f64 != f64) {
+      set_err(ctx, "one batch cannot mix FP32-packed and FP64 datasets");
+      return MU_E_UNSUPPORTED;
+    }
+  }
+  hipSetDevice(ctx->device);
+  int64_t n_blocks = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    if ((st = const_cast<mu_data *>(data[j])->build_tiles(ctx->tile_bins)) != MU_OK) return st;
+    n_blocks += data[j]->n_tiles;
+  }
+  if (n_blocks > INT32_MAX) {
+    set_err(ctx, "launch needs more than 2^31 workgroups");
+    return MU_E_UNSUPPORTED;
+  }
+  return run_batch(ctx, n_jobs, data, th, cost_kind, ld, params, mem, cost, grad, n_blocks);
+}
+
+namespace mu {
+
+mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,
+                    int cost_kind, int32_t ld, const double *params, unsigned mem, double *cost, double *grad,
+                    int64_t n_blocks) {
+  mu_status st;
+  hipError_t e;
+  const size_t n_p = (size_t)n_jobs * ld;
+  const size_t n_c = (size_t)n_jobs;
+  const size_t n_g = grad ? (size_t)n_jobs * ld : 0;
+  const size_t jobs_bytes = (size_t)n_jobs * sizeof(DevJob);
+  const size_t map_bytes = (size_t)n_blocks * sizeof(int32_t);
+  const size_t meta = ((jobs_bytes + map_bytes + 255) & ~size_t(255));
+  const size_t up_bytes = meta + (mem == MU_MEM_HOST ? n_p * sizeof(double) : 0);
+  if ((st = ctx->djobs.ensure(ctx, up_bytes, false)) != MU_OK) return st;
+  if ((st = ctx->staging.ensure(ctx, up_bytes)) != MU_OK) return st;
+  if ((st = ctx->partial.ensure(ctx, (size_t)n_blocks * kSlot * sizeof(double), false)) != MU_OK) return st;
+  if (mem == MU_MEM_HOST) {
+    if ((st = ctx->dout.ensure(ctx, (n_c + n_g) * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->staging_out.ensure(ctx, (n_c + n_g) * sizeof(double))) != MU_OK) return st;
+  }
+  ctx->wait_staging();
+  char *up = static_cast<char *>(ctx->staging.ptr);
+  char *dup = static_cast<char *>(ctx->djobs.ptr);
+  DevJob *jobs = reinterpret_cast<DevJob *>(up);
+  int32_t *bj = reinterpret_cast<int32_t *>(up + jobs_bytes);
+  const double *dp = params;
+  if (mem == MU_MEM_HOST) {
+    std::memcpy(up + meta, params, n_p * sizeof(double));
+    dp = reinterpret_cast<const double *>(dup + meta);
+  }
+  double *dc = cost, *dg = grad;
+  if (mem == MU_MEM_HOST) {
+    dc = static_cast<double *>(ctx->dout.ptr);
+    dg = grad ? dc + n_c : nullptr;
+  }
+  // jobs keep their order (and partial slots); workgroups are grouped by
+  // theory shape so each group runs its compiled specialisation
+  int32_t slot_base = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    DevJob &J = jobs[j];
+    std::memset(&J, 0, sizeof J);
+    J.th = th[j]->d_th;
+    J.histos = data[j]->d_histos;
+    J.counts = data[j]->counts;
+    J.tiles = data[j]->d_tiles;
+    J.p = dp + (size_t)j * ld;
+    J.cost_out = dc + j;
+    J.histo_out = nullptr;
+    J.grad_out = dg ? dg + (size_t)j * ld : nullptr;
+    J.model_out = nullptr;
+    J.n_tiles = data[j]->n_tiles;
+    J.n_histo = data[j]->n_histo;
+    J.tile_base = slot_base;
+    slot_base += J.n_tiles;
+  }
+  int group_first[kShapeCount + 1];
+  int32_t filled = 0;
+  for (int shp = 0; shp < kShapeCount; ++shp) {
+    group_first[shp] = filled;
+    for (int j = 0; j < n_jobs; ++j) {
+      const int js = ctx->specialize ? th[j]->shape : kShapeGeneric;
+      if (js != shp) continue;
+      jobs[j].block_base = filled - group_first[shp];
+      for (int k = 0; k < jobs[j].n_tiles; ++k) bj[filled + k] = j;
+      filled += jobs[j].n_tiles;
+    }
+  }
+  group_first[kShapeCount] = filled;
+  e = hipMemcpyAsync(dup, up, up_bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(jobs)");
+  ctx->mark_staging();
+  for (int shp = 0; shp < kShapeCount; ++shp) {
+    const int nb = group_first[shp + 1] - group_first[shp];
+    if (nb == 0) continue;
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.jobs = reinterpret_cast<const DevJob *>(dup);
+    a.block_job = reinterpret_cast<const int32_t *>(dup + jobs_bytes) + group_first[shp];
+    a.n_blocks = nb;
+    a.cost_kind = cost_kind;
+    a.anchor_every = ctx->anchor_every;
+    a.partial = static_cast<double *>(ctx->partial.ptr);
+    e = launch_eval(a, grad ? kModeGrad : kModeCost, data[0]->f64, shp, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched evaluation launch");
+  }
+  {
+    LaunchArgs m;
+    std::memset(&m, 0, sizeof m);
+    m.jobs = reinterpret_cast<const DevJob *>(dup);
+    m.partial = static_cast<double *>(ctx->partial.ptr);
+    e = launch_merge(m, grad ? kModeGrad : kModeCost, n_jobs, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
+  }
+  if (mem == MU_MEM_HOST) {
+    e = hipMemcpyAsync(ctx->staging_out.ptr, ctx->dout.ptr, (n_c + n_g) * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(results)");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    const double *o = static_cast<const double *>(ctx->staging_out.ptr);
+    std::memcpy(cost, o, n_c * sizeof(double));
+    // entries past a job's n_par are left untouched
+    if (grad)
+      for (int j = 0; j < n_jobs; ++j)
+        std::memcpy(grad + (size_t)j * ld, o + n_c + (size_t)j * ld, th[j]->h.n_par * sizeof(double));
+  }
+  return MU_OK;
+}
+
+}  // namespace mu

@@ -1,0 +1,702 @@
+// Fused theory-evaluate-and-reduce kernels for gfx950.
+//
+// One workgroup (256 lanes, four wave64s) takes one tile: a run of consecutive
+// fit-range bins of one histogram for one parameter vector.  Lane l of the
+// tile reads bins l, l + 256, l + 512, ... so that every step of the
+// workgroup streams 256 consecutive counts (1 KiB of FP32) from memory.
+//
+// Per bin the lane evaluates the theory program (Listings 2-3), the histogram
+// model (Eq. 1) and the cost term (Eq. 2 or Eq. 3); in gradient mode it also
+// accumulates r dN/dR for every resolved scalar R (r = d term / dN).
+//
+// Evaluation by anchored recurrences.  The time grid is uniform, so along one
+// lane (time step h = 256 dt) every primitive except the stretched
+// exponential obeys an exact multiplicative recurrence:
+//   e^(-t/tau), se:  v(t+h) = v(t) e^(-lambda h)                (geometric)
+//   sg, stg:         g(t+h) = g(t) q(t),  q(t+h) = q(t) e^(-(sigma h)^2)
+//                    with q(t) = e^(-sigma^2 h (t + h/2))       (second order)
+//   tf:              (cos, sin)(theta + omega h) = rotation by omega h
+// Each lane evaluates the exact values at its first bin (the anchor) and
+// re-anchors every `anchor_every` steps; the step constants are uniform and
+// computed once per workgroup.  Rounding drift grows like k eps for the
+// geometric and rotation sequences and k^2 eps / 2 for the Gaussian one, so
+// at most 64 steps between anchors keep every factor within ~5e-13 relative of
+// its directly evaluated value.  ge (beta free) is evaluated directly.
+//
+// Reduction: per lane a plain FP64 sum over its <= 256 bins, then compensated
+// (TwoSum) merges across the wave, the workgroup and the tiles of the job.
+// Each tile writes its own slot; a second, one-workgroup-per-job kernel merges
+// the job's slots in a fixed order, so results are bitwise reproducible and
+// no atomics or device-scope fences are used.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mu_internal.h"
+
+// Every fused multiply-add below is written out: automatic contraction could
+// round the cost pass and the gradient pass differently.
+#pragma clang fp contract(off)
+
+namespace mu {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kThird = 1.0 / 3.0;
+constexpr double kTwoThird = 2.0 / 3.0;
+constexpr int kSlots = kMaxT * kMaxFT;
+
+struct Pair {
+  double s, c;
+};
+struct D2 {
+  double a, b;
+};
+
+// Theory shapes.  A fixed shape hard-wires the number of terms, the factors
+// of each term and their primitives, so the compiler keeps only the states,
+// step constants and accumulators that shape needs; the generic shape reads
+// them from the theory program at run time.
+// Structure of a theory program held in scalar registers by every workgroup.
+struct TStruct {
+  int nt;
+  int nf[kMaxT];
+  int prim[kMaxT][kMaxFT];
+};
+
+struct ShapeGeneric {
+  static constexpr bool kFixed = false;
+  __device__ static int nt(const TStruct &ts) { return ts.nt; }
+  __device__ static int nf(const TStruct &ts, int k) { return ts.nf[k]; }
+  __device__ static int prim(const TStruct &ts, int k, int f) { return ts.prim[k][f]; }
+};
+
+template <int NT, int NF0, int P00, int P01, int NF1, int P10, int P11>
+struct ShapeFixed {
+  static constexpr bool kFixed = true;
+  __device__ static constexpr int nt(const TStruct &) { return NT; }
+  __device__ static constexpr int nf(const TStruct &, int k) { return k == 0 ? NF0 : (k == 1 ? NF1 : 0); }
+  __device__ static constexpr int prim(const TStruct &, int k, int f) {
+    return k == 0 ? (f == 0 ? P00 : P01) : (f == 0 ? P10 : P11);
+  }
+};
+
+using ShapeExpCos = ShapeFixed<1, 2, MU_SE, MU_TF, 0, 0, 0>;
+using ShapeGaussCos = ShapeFixed<1, 2, MU_SG, MU_TF, 0, 0, 0>;
+using ShapeStg = ShapeFixed<1, 1, MU_STG, 0, 0, 0, 0>;
+using ShapeExpStg = ShapeFixed<2, 1, MU_SE, 0, 1, MU_STG, 0>;
+using ShapeExpCosStg = ShapeFixed<2, 2, MU_SE, MU_TF, 1, MU_STG, 0>;
+
+// Knuth's TwoSum applied to two compensated pairs.
+__device__ __forceinline__ Pair pair_add(Pair x, Pair y) {
+  double s = x.s + y.s;
+  double bp = s - x.s;
+  double e = (x.s - (s - bp)) + (y.s - bp);
+  return Pair{s, x.c + y.c + e};
+}
+
+// Value of a compensated pair; an infinite sum keeps its sign (the correction
+// term of TwoSum is NaN once the sum overflows to infinity).
+__device__ __forceinline__ double pair_value(Pair x) { return isinf(x.s) ? x.s : x.s + x.c; }
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+
+__device__ __forceinline__ Pair wave_pair_sum(Pair p) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    Pair o{shfl_xor_d(p.s, m), shfl_xor_d(p.c, m)};
+    // both lanes of a pair combine (lower lane, upper lane): identical results
+    p = ((threadIdx.x & m) == 0) ? pair_add(p, o) : pair_add(o, p);
+  }
+  return p;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    double o = shfl_xor_d(v, m);
+    v = ((threadIdx.x & m) == 0) ? (v + o) : (o + v);
+  }
+  return v;
+}
+
+// Uniform copy of lane `src`'s value (scalar registers).
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Out-of-line transcendentals: they run at anchors and in the workgroup
+// prologue, and one copy each keeps the kernels small.
+__device__ __attribute__((noinline)) double x_exp(double x) { return exp(x); }
+__device__ __attribute__((noinline)) D2 x_sincos(double x) {
+  D2 r;
+  sincos(x, &r.b, &r.a);  // a = cos, b = sin
+  return r;
+}
+// stretched exponential e^(-(l t)^b) and (l t)^b ln(l t)
+__device__ __attribute__((noinline)) D2 x_ge(double lt, double beta) {
+  const double xb = pow(lt, beta);
+  D2 r;
+  r.a = exp(-xb);
+  r.b = (lt > 0.0) ? xb * log(lt) : 0.0;
+  return r;
+}
+__device__ __attribute__((noinline)) double x_pow(double x, double y) { return pow(x, y); }
+
+// ------------------------------------------------------------------ resolve
+
+__device__ double resolve_ref(const DevTheory *th, DevRef r, const double *p, int row) {
+  if (r.kind == MU_REF_PAR) return p[th->map[row * th->n_slots + r.slot]];
+  if (r.kind == MU_REF_FUN) {
+    const int i = th->map[row * th->n_slots + r.slot];
+    const double *Fi = th->F + (int64_t)i * th->n_par;
+    double s = 0.0;
+    for (int k = 0; k < th->n_par; ++k) s = fma(Fi[k], p[k], s);
+    return s + th->f0[i];
+  }
+  if (r.kind == MU_REF_LIT) return r.lit;
+  return 0.0;
+}
+
+// ----------------------------------------------------- primitive recurrences
+
+// Step constant w (0 or 1) of a primitive for the lane step h.
+__device__ __forceinline__ double step_const(int kind, int w, double a0, double a1, double h) {
+  switch (kind) {
+    case MU_SE:
+      return w == 0 ? x_exp(-a0 * h) : 0.0;
+    case MU_SG:
+    case MU_STG: {
+      const double x = a0 * h;
+      return w == 0 ? x_exp(-(x * x)) : 0.0;
+    }
+    case MU_TF: {
+      const D2 cs = x_sincos(kTwoPi * a1 * h);
+      return w == 0 ? cs.a : cs.b;
+    }
+    default:
+      return 0.0;
+  }
+}
+
+// Exact state at time t (anchor).
+__device__ __forceinline__ void anchor(int kind, double t, double a0, double a1, double h, double &s0, double &s1) {
+  switch (kind) {
+    case MU_SE:
+      s0 = x_exp(-a0 * t);
+      s1 = 0.0;
+      break;
+    case MU_SG:
+    case MU_STG: {
+      const double x = a0 * t;
+      s0 = x_exp(-0.5 * (x * x));
+      s1 = x_exp(-(a0 * a0) * h * (t + 0.5 * h));
+      break;
+    }
+    case MU_TF: {
+      const D2 cs = x_sincos(kTwoPi * a1 * t + a0);
+      s0 = cs.a;
+      s1 = cs.b;
+      break;
+    }
+    default:
+      s0 = s1 = 0.0;
+      break;
+  }
+}
+
+// Advance the state by one lane step.
+__device__ __forceinline__ void advance(int kind, double c0, double c1, double &s0, double &s1) {
+  switch (kind) {
+    case MU_SE:
+      s0 *= c0;
+      break;
+    case MU_SG:
+    case MU_STG:
+      s0 *= s1;
+      s1 *= c0;
+      break;
+    case MU_TF: {
+      const double c = fma(s0, c0, -(s1 * c1));
+      const double s = fma(s1, c0, s0 * c1);
+      s0 = c;
+      s1 = s;
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Primitive value at time t from its state.
+__device__ __forceinline__ double value(int kind, double t, double a0, double a1, double s0) {
+  switch (kind) {
+    case MU_GE:
+      return x_exp(-x_pow(a0 * t, a1));
+    case MU_STG: {
+      const double x = a0 * t;
+      return fma(kTwoThird * fma(-x, x, 1.0), s0, kThird);
+    }
+    default:  // se, sg, tf: the state itself
+      return s0;
+  }
+}
+
+// Primitive value and derivatives in its arguments, from its state.
+__device__ __forceinline__ double value_grad(int kind, double t, double a0, double a1, double s0, double s1,
+                                             double &d0, double &d1) {
+  switch (kind) {
+    case MU_SE:
+      d0 = -t * s0;
+      d1 = 0.0;
+      return s0;
+    case MU_GE: {
+      const double x = a0 * t;
+      const D2 v = x_ge(x, a1);  // v.a = e^(-x^b), v.b = x^b ln x
+      if (x > 0.0) {
+        d0 = -a1 * x_pow(x, a1) / a0 * v.a;
+        d1 = -v.b * v.a;
+      } else {
+        d0 = (a1 == 1.0) ? -t : 0.0;
+        d1 = 0.0;
+      }
+      return v.a;
+    }
+    case MU_SG:
+      d0 = -a0 * t * t * s0;
+      d1 = 0.0;
+      return s0;
+    case MU_STG: {
+      const double x = a0 * t;
+      const double s2 = x * x;
+      d0 = kTwoThird * a0 * t * t * (s2 - 3.0) * s0;
+      d1 = 0.0;
+      return fma(kTwoThird * fma(-x, x, 1.0), s0, kThird);
+    }
+    default:  // MU_TF: state (cos, sin)
+      d0 = -s1;
+      d1 = -kTwoPi * t * s1;
+      return s0;
+  }
+}
+
+// Per-bin cost term (Eq. 2 / Eq. 3) and its derivative in N.
+template <int COST, bool WANT_DN>
+__device__ __forceinline__ double cost_term(double d, double N, double &dN) {
+  if (COST == MU_COST_CHI2) {
+    const double v = d > 0.0 ? d : 1.0;
+    // 1/v: hardware reciprocal refined by one Newton step (< 1 ulp + rounding)
+    double iv = __builtin_amdgcn_rcp(v);
+    iv = fma(iv, fma(-v, iv, 1.0), iv);
+    const double diff = d - N;
+    if (WANT_DN) dN = -2.0 * diff * iv;
+    return diff * diff * iv;
+  } else {
+    if (d > 0.0) {
+      const double q = d / N;
+      if (WANT_DN) dN = 2.0 * (1.0 - q);
+      if (!(N > 0.0)) return (N <= 0.0) ? INFINITY : N;  // NaN stays NaN
+      return 2.0 * ((N - d) + d * log(q));
+    }
+    if (WANT_DN) dN = 2.0;
+    return 2.0 * N;
+  }
+}
+
+template <typename CT>
+__device__ __forceinline__ double load_count(const void *counts, int64_t i) {
+  return (double)(static_cast<const CT *>(counts)[i]);
+}
+
+__device__ __forceinline__ DevJob job_of(const LaunchArgs &a, int b, int &job) {
+  if (a.jobs == nullptr) {
+    job = b / a.tmpl.n_tiles;
+    DevJob J = a.tmpl;
+    J.p += job * a.p_stride;
+    J.cost_out += job;
+    if (J.histo_out) J.histo_out += job * a.histo_stride;
+    if (J.grad_out) J.grad_out += job * a.grad_stride;
+    J.tile_base = job * a.tmpl.n_tiles;
+    J.block_base = J.tile_base;
+    return J;
+  }
+  job = a.block_job[b];
+  return a.jobs[job];
+}
+
+// ------------------------------------------------------------ merge (last WG)
+
+// Merge the tile slots of job J in a fixed order and write its outputs.
+template <int MODE>
+__device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
+  __shared__ Pair red[kBlock / 64];
+  const int tid = threadIdx.x;
+  const double *P = a.partial + (int64_t)J.tile_base * kSlot;
+
+  // total cost: strided fixed assignment of tiles to threads, then a tree
+  Pair acc{0.0, 0.0};
+  for (int k = tid; k < J.n_tiles; k += kBlock) acc = pair_add(acc, Pair{P[k * kSlot], P[k * kSlot + 1]});
+  acc = wave_pair_sum(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    Pair t = red[0];
+    for (int w = 1; w < kBlock / 64; ++w) t = pair_add(t, red[w]);
+    J.cost_out[0] = pair_value(t);
+  }
+
+  // per-histogram cost
+  if (J.histo_out) {
+    for (int h = tid; h < J.n_histo; h += kBlock) {
+      const int k0 = J.histos[h].tile0;
+      const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
+      Pair q{0.0, 0.0};
+      for (int k = k0; k < k1; ++k) q = pair_add(q, Pair{P[k * kSlot], P[k * kSlot + 1]});
+      J.histo_out[h] = pair_value(q);
+    }
+  }
+
+  if constexpr (MODE == kModeGrad) {
+    // chain rule through the map / function array:
+    //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's tiles
+    constexpr int HC = 32;
+    __shared__ double gR[HC][kRS];
+    __shared__ double acc_s[MU_MAX_PAR];
+    __shared__ double acc_c[MU_MAX_PAR];
+    const DevTheory *th = J.th;
+    const int n_par = th->n_par;
+    for (int k = tid; k < n_par; k += kBlock) {
+      acc_s[k] = 0.0;
+      acc_c[k] = 0.0;
+    }
+    for (int h0 = 0; h0 < J.n_histo; h0 += HC) {
+      const int nh = min(HC, J.n_histo - h0);
+      __syncthreads();
+      for (int w = tid; w < nh * kRS; w += kBlock) {
+        const int hh = w / kRS, r = w % kRS;
+        const int h = h0 + hh;
+        double s = 0.0;
+        if (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN) {
+          const int k0 = J.histos[h].tile0;
+          const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
+          Pair q{0.0, 0.0};
+          for (int k = k0; k < k1; ++k) q = pair_add(q, Pair{P[k * kSlot + 2 + r], 0.0});
+          s = pair_value(q);
+        }
+        gR[hh][r] = s;
+      }
+      __syncthreads();
+      for (int k = tid; k < n_par; k += kBlock) {
+        Pair q{acc_s[k], acc_c[k]};
+        for (int hh = 0; hh < nh; ++hh) {
+          const int row = J.histos[h0 + hh].map_row;
+          for (int r = 0; r < kRS; ++r) {
+            const DevRef ref = th->rref[r];
+            if (ref.kind == MU_REF_PAR) {
+              if (th->map[row * th->n_slots + ref.slot] == k) q = pair_add(q, Pair{gR[hh][r], 0.0});
+            } else if (ref.kind == MU_REF_FUN) {
+              const int i = th->map[row * th->n_slots + ref.slot];
+              q = pair_add(q, Pair{gR[hh][r] * th->F[(int64_t)i * n_par + k], 0.0});
+            }
+          }
+        }
+        acc_s[k] = q.s;
+        acc_c[k] = q.c;
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < n_par; k += kBlock) J.grad_out[k] = pair_value(Pair{acc_s[k], acc_c[k]});
+  }
+}
+
+// ------------------------------------------------------------------- kernel
+
+template <int COST, int MODE, typename CT, typename Sh>
+__global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  int job;
+  const DevJob J = job_of(a, b, job);
+  const DevTile T = J.tiles[b - J.block_base];
+  const DevHisto H = J.histos[T.histo];
+  const DevTheory *th = J.th;
+  const int row = H.map_row;
+  TStruct ts;
+  if constexpr (!Sh::kFixed) {
+    ts.nt = __builtin_amdgcn_readfirstlane(th->n_terms);
+#pragma unroll
+    for (int k = 0; k < kMaxT; ++k) {
+      ts.nf[k] = __builtin_amdgcn_readfirstlane(th->nf[k]);
+#pragma unroll
+      for (int f = 0; f < kMaxFT; ++f) ts.prim[k][f] = __builtin_amdgcn_readfirstlane(th->prim[k][f]);
+    }
+  }
+  const int n_terms = Sh::nt(ts);
+  const double neg_inv_tau = bcast(th->neg_inv_tau, 0);
+  double coef[kMaxT];
+#pragma unroll
+  for (int k = 0; k < kMaxT; ++k) coef[k] = k < n_terms ? bcast(th->coef[k], 0) : 0.0;
+
+  const int lane = tid & 63;
+  // resolved scalars of this (vector, histogram): lane r of every wave
+  // resolves scalar r, then each is broadcast to scalar registers
+  double R[kRS];
+  {
+    const double mine = lane < kRS ? resolve_ref(th, th->rref[lane], J.p, row) : 0.0;
+#pragma unroll
+    for (int r = 0; r < kRS; ++r) R[r] = bcast(mine, r);
+  }
+  const double n0 = R[0], nbkg = R[1];
+  const double h = H.dt * (double)kBlock;  // lane step
+
+  // uniform step constants, one transcendental per lane of every wave, then
+  // broadcast within the wave: lane 0: lifetime ratio; lane 1 + 2 s + w:
+  // constant w of factor slot s
+  double cst = 0.0;
+  if (lane == 0) {
+    cst = x_exp(neg_inv_tau * h);
+  } else if (lane <= 2 * kSlots) {
+    const int s = (lane - 1) >> 1, w = (lane - 1) & 1;
+    const int k = s / kMaxFT, f = s % kMaxFT;
+    if (k < n_terms && f < Sh::nf(ts, k)) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q)
+        if (q == s) {
+          a0 = R[kArg0 + 2 * q];
+          a1 = R[kArg0 + 2 * q + 1];
+        }
+      cst = step_const(Sh::prim(ts, k, f), w, a0, a1, h);
+    }
+  }
+  const double rE = bcast(cst, 0);
+  double c0[kSlots], c1[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    c0[s] = bcast(cst, 1 + 2 * s);
+    c1[s] = bcast(cst, 2 + 2 * s);
+  }
+
+  // per-lane states
+  double E = 0.0;
+  double s0[kSlots], s1[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) s0[s] = s1[s] = 0.0;
+
+  double lane_cost = 0.0;
+  double g[kRS];
+#pragma unroll
+  for (int r = 0; r < kRS; ++r) g[r] = 0.0;
+
+  const int64_t n_first = H.first + T.begin + tid;  // this lane's first bin
+  const double t_first = ((double)n_first - H.t0_bin) * H.dt;
+  const int n_steps = (T.n - tid + kBlock - 1) / kBlock;  // bins of this lane (may be 0)
+  const int every = a.anchor_every;
+
+  for (int k0 = 0; k0 < n_steps; k0 += every) {
+    // exact re-evaluation (anchor) at the first step of the segment
+    {
+      const double t = fma((double)k0, h, t_first);
+      E = x_exp(neg_inv_tau * t);
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int kt = s / kMaxFT, f = s % kMaxFT;
+        if (kt < n_terms && f < Sh::nf(ts, kt))
+          anchor(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
+      }
+    }
+    const int k1 = min(n_steps, k0 + every);
+  for (int k = k0; k < k1; ++k) {
+    const double t = fma((double)k, h, t_first);
+    const int64_t idx = H.off + T.begin + tid + (int64_t)k * kBlock;
+
+    if constexpr (MODE != kModeGrad) {
+      double A = 0.0;
+#pragma unroll
+      for (int kt = 0; kt < kMaxT; ++kt) {
+        if (kt < n_terms) {
+          double prod = 1.0;
+#pragma unroll
+          for (int f = 0; f < kMaxFT; ++f) {
+            const int s = kt * kMaxFT + f;
+            if (f < Sh::nf(ts, kt)) prod *= value(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], s0[s]);
+          }
+          A = fma(coef[kt] * R[2 + kt], prod, A);
+        }
+      }
+      const double N = fma(n0 * E, 1.0 + A, nbkg);
+      if constexpr (MODE == kModeModel) {
+        J.model_out[idx] = N;
+      } else {
+        double dN;
+        lane_cost += cost_term<COST, false>(load_count<CT>(J.counts, idx), N, dN);
+      }
+    } else {
+      double val[kSlots], d0[kSlots], d1[kSlots];
+      double tprod[kMaxT];
+      double A = 0.0;
+#pragma unroll
+      for (int kt = 0; kt < kMaxT; ++kt) {
+        tprod[kt] = 1.0;
+        if (kt < n_terms) {
+#pragma unroll
+          for (int f = 0; f < kMaxFT; ++f) {
+            const int s = kt * kMaxFT + f;
+            val[s] = 1.0;
+            d0[s] = d1[s] = 0.0;
+            if (f < Sh::nf(ts, kt)) {
+              val[s] = value_grad(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], s0[s], s1[s], d0[s],
+                                  d1[s]);
+              tprod[kt] *= val[s];
+            }
+          }
+          A = fma(coef[kt] * R[2 + kt], tprod[kt], A);
+        }
+      }
+      const double N = fma(n0 * E, 1.0 + A, nbkg);
+      double dN;
+      lane_cost += cost_term<COST, true>(load_count<CT>(J.counts, idx), N, dN);
+      const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
+      const double rNE = rE * n0;  // r N0 e^(-t/tau)
+      g[0] = fma(rE, 1.0 + A, g[0]);
+      g[1] += dN;
+#pragma unroll
+      for (int kt = 0; kt < kMaxT; ++kt) {
+        if (kt < n_terms) {
+          const double ck = coef[kt];
+          g[2 + kt] = fma(rNE * ck, tprod[kt], g[2 + kt]);
+          const double ca = rNE * ck * R[2 + kt];
+#pragma unroll
+          for (int f = 0; f < kMaxFT; ++f) {
+            const int s = kt * kMaxFT + f;
+            if (f < Sh::nf(ts, kt)) {
+              double others = ca;
+#pragma unroll
+              for (int f2 = 0; f2 < kMaxFT; ++f2)
+                if (f2 != f && f2 < Sh::nf(ts, kt)) others *= val[kt * kMaxFT + f2];
+              g[kArg0 + 2 * s] = fma(others, d0[s], g[kArg0 + 2 * s]);
+              g[kArg0 + 2 * s + 1] = fma(others, d1[s], g[kArg0 + 2 * s + 1]);
+            }
+          }
+        }
+      }
+    }
+
+    // advance every state by one lane step
+    E *= rE;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int kt = s / kMaxFT, f = s % kMaxFT;
+      if (kt < n_terms && f < Sh::nf(ts, kt)) advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+    }
+  }
+  }
+  if constexpr (MODE == kModeModel) return;
+
+  // workgroup reduction of the cost (compensated) and the gradient (fixed tree)
+  __shared__ Pair wred[kBlock / 64];
+  __shared__ double gred[kBlock / 64][kRS];
+  const int w = tid >> 6;
+  Pair pc = wave_pair_sum(Pair{lane_cost, 0.0});
+  if ((tid & 63) == 0) wred[w] = pc;
+  if constexpr (MODE == kModeGrad) {
+#pragma unroll
+    for (int r = 0; r < kRS; ++r) {
+      if (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN) {
+        const double s = wave_sum(g[r]);
+        if ((tid & 63) == 0) gred[w][r] = s;
+      }
+    }
+  }
+  __syncthreads();
+  // the job's slots are global across the per-shape launches of one batch
+  double *slot = a.partial + ((int64_t)J.tile_base + (b - J.block_base)) * kSlot;
+  if (tid == 0) {
+    Pair t = wred[0];
+    for (int q = 1; q < kBlock / 64; ++q) t = pair_add(t, wred[q]);
+    slot[0] = t.s;
+    slot[1] = t.c;
+  }
+  if constexpr (MODE == kModeGrad) {
+    if (tid < kRS) {
+      double s = gred[0][tid];
+      for (int q = 1; q < kBlock / 64; ++q) s += gred[q][tid];
+      slot[2 + tid] = s;
+    }
+  }
+}
+
+// One workgroup per job: fixed-order merge of the job's tile slots.  It runs
+// as its own launch after the evaluation kernel, whose completion makes every
+// slot visible; no fences or atomics are needed inside the evaluation kernel.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void merge_kernel(LaunchArgs a) {
+  int job = blockIdx.x;
+  DevJob J;
+  if (a.jobs == nullptr) {
+    J = a.tmpl;
+    J.p += job * a.p_stride;
+    J.cost_out += job;
+    if (J.histo_out) J.histo_out += job * a.histo_stride;
+    if (J.grad_out) J.grad_out += job * a.grad_stride;
+    J.tile_base = job * a.tmpl.n_tiles;
+  } else {
+    J = a.jobs[job];
+  }
+  merge_job<MODE>(a, J);
+}
+
+template <int COST, int MODE, typename Sh>
+hipError_t launch_shape(const LaunchArgs &a, int count_f64, hipStream_t s) {
+  dim3 grid(a.n_blocks), block(kBlock);
+  if (count_f64)
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, double, ShapeGeneric>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, float, Sh>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  dim3 grid(n_jobs), block(kBlock);
+  if (mode == kModeGrad)
+    hipLaunchKernelGGL((merge_kernel<kModeGrad>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((merge_kernel<kModeCost>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <int COST, int MODE>
+hipError_t launch_typed(const LaunchArgs &a, int count_f64, int shape, hipStream_t s) {
+  switch (shape) {
+    case kShapeExpCos: return launch_shape<COST, MODE, ShapeExpCos>(a, count_f64, s);
+    case kShapeGaussCos: return launch_shape<COST, MODE, ShapeGaussCos>(a, count_f64, s);
+    case kShapeStg: return launch_shape<COST, MODE, ShapeStg>(a, count_f64, s);
+    case kShapeExpStg: return launch_shape<COST, MODE, ShapeExpStg>(a, count_f64, s);
+    case kShapeExpCosStg: return launch_shape<COST, MODE, ShapeExpCosStg>(a, count_f64, s);
+    default: return launch_shape<COST, MODE, ShapeGeneric>(a, count_f64, s);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s) {
+  if (a.n_blocks <= 0) return hipSuccess;
+  if (a.anchor_every < 1) return hipErrorInvalidValue;
+  if (mode == kModeModel) return launch_typed<MU_COST_CHI2, kModeModel>(a, count_f64, shape, s);
+  if (a.cost_kind == MU_COST_CHI2)
+    return mode == kModeGrad ? launch_typed<MU_COST_CHI2, kModeGrad>(a, count_f64, shape, s)
+                             : launch_typed<MU_COST_CHI2, kModeCost>(a, count_f64, shape, s);
+  return mode == kModeGrad ? launch_typed<MU_COST_POISSON, kModeGrad>(a, count_f64, shape, s)
+                           : launch_typed<MU_COST_POISSON, kModeCost>(a, count_f64, shape, s);
+}
+
+}  // namespace mu

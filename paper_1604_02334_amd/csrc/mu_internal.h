@@ -1,0 +1,111 @@
+// Internal structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/mu.h"
+
+namespace mu {
+
+constexpr int kMaxT = MU_MAX_TERMS;
+constexpr int kMaxFT = MU_MAX_FACTORS_PER_TERM;
+// Resolved scalars of one (vector, histogram) pair, in a fixed order:
+// 0 N0, 1 Nbkg, 2..2+kMaxT-1 term amplitudes, then argument a of factor i of
+// term k at kArg0 + (k * kMaxFT + i) * 2 + a.
+constexpr int kArg0 = 2 + kMaxT;
+constexpr int kRS = kArg0 + kMaxT * kMaxFT * 2;  // 30
+// Partial slot of one tile: cost (s, c) then kRS gradient components.
+constexpr int kSlot = 2 + kRS;  // 32 doubles
+constexpr int kBlock = 256;     // threads per evaluation workgroup
+constexpr int kRefNone = -1;
+
+constexpr __host__ __device__ int arg_index(int k, int i, int a) { return kArg0 + (k * kMaxFT + i) * 2 + a; }
+
+struct DevRef {
+  int32_t kind;  // mu_ref_kind, or kRefNone for an unused resolved scalar
+  int32_t slot;
+  double lit;
+};
+
+struct DevTheory {
+  double tau_mu;
+  double neg_inv_tau;  // -1 / tau_mu
+  int32_t n_terms, n_par, n_fun, n_rows, n_slots, pad0;
+  int32_t nf[kMaxT];
+  int32_t prim[kMaxT][kMaxFT];
+  double coef[kMaxT];
+  DevRef rref[kRS];    // reference behind each resolved scalar
+  const int32_t *map;  // device [n_rows][n_slots]
+  const double *F;     // device [n_fun][n_par]
+  const double *f0;    // device [n_fun]
+};
+
+struct DevHisto {
+  int64_t off;    // offset of the first fit-range bin in the counts array
+  int64_t n;      // fit-range bins
+  int64_t first;  // index of the first fit-range bin in the histogram
+  double t0_bin;
+  double dt;
+  int32_t map_row;
+  int32_t tile0;  // first tile of this histogram in the dataset's tile table
+};
+
+struct DevTile {
+  int64_t begin;  // first bin, relative to the histogram's fit range
+  int32_t histo;
+  int32_t n;      // bins in this tile
+};
+
+// One evaluation job: a parameter vector over one dataset and theory.
+struct DevJob {
+  const DevTheory *th;
+  const DevHisto *histos;
+  const void *counts;
+  const DevTile *tiles;
+  const double *p;       // parameter vector (device)
+  double *cost_out;      // [1]
+  double *histo_out;     // [n_histo] or null
+  double *grad_out;      // [n_par] or null
+  double *model_out;     // per-bin N (model evaluation) or null
+  int32_t n_tiles;
+  int32_t n_histo;
+  int32_t tile_base;     // first partial slot of this job
+  int32_t block_base;    // first workgroup of this job in its launch
+};
+
+enum Mode : int { kModeCost = 0, kModeGrad = 1, kModeModel = 2 };
+
+// Theory shapes with a compiled specialisation (see mu_eval.hip).
+enum Shape : int {
+  kShapeGeneric = 0,
+  kShapeExpCos = 1,    // A se(lambda) tf(phi, nu)
+  kShapeGaussCos = 2,  // A sg(sigma) tf(phi, nu)
+  kShapeStg = 3,       // A stg(sigma)
+  kShapeExpStg = 4,    // A1 se(lambda) + A2 stg(sigma)
+  kShapeExpCosStg = 5,  // A1 se(lambda) tf(phi, nu) + A2 stg(sigma)
+  kShapeCount = 6
+};
+
+struct LaunchArgs {
+  // Uniform launch (jobs == null): job v is `tmpl` with its parameter vector
+  // and outputs advanced by v strides, and owns workgroups
+  // [v * tmpl.n_tiles, (v + 1) * tmpl.n_tiles).
+  DevJob tmpl;
+  int64_t p_stride, grad_stride, histo_stride;
+  // Mapped launch: explicit jobs and a workgroup -> job table.
+  const DevJob *jobs;
+  const int32_t *block_job;
+  int32_t n_blocks;
+  int32_t cost_kind;
+  int32_t anchor_every;  // lane steps between exact re-evaluations, 1..64
+  int32_t pad0;
+  double *partial;    // [total tiles of all jobs][kSlot]
+};
+
+hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);
+// Merge the tile slots of jobs [0, n_jobs) of `a` (uniform or mapped).
+hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s);
+
+}  // namespace mu

@@ -1,0 +1,321 @@
+"""GPU parity of the fused evaluation kernels against the FP64 oracle.
+
+Bar (written here, derived from the target): every cost within a relative
+1e-10 of the oracle's exactly rounded sum; gradients within 1e-10 of the
+scale sum_n |r_n dN_n/dp_k| of the oracle's gradient and within 1e-6 of
+central finite differences; model values within 1e-13 relative."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import model
+from paper_1604_02334_amd import api
+
+from _workloads import c1, c2, c3, counts_for, perturbed
+
+pytestmark = pytest.mark.gpu
+REL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _mk(ctx, theory, histos, counts):
+    return api.Theory(ctx, theory), api.Data(ctx, histos, counts)
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_c1_cost_parity(ctx, kind):
+    _say("c1 cost", kind)
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    P = np.stack([cfg["p_true"], perturbed(cfg["p_true"], 1e-2, 1), perturbed(cfg["p_true"], 0.2, 2)])
+    got = api.chi2_eval(ctx, d, th, P, kind)
+    for v in range(P.shape[0]):
+        ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v], kind)
+        assert abs(got[v] - ref) <= REL * abs(ref), (v, got[v], ref)
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_c2_cost_and_per_histo_parity(ctx, kind):
+    _say("c2 cost", kind)
+    cfg, counts = c2()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    P = np.stack([cfg["p_true"], perturbed(cfg["p_true"], 1e-2, 3)])
+    got, ph = api.chi2_eval(ctx, d, th, P, kind, per_histo=True)
+    for v in range(P.shape[0]):
+        ref_h = model.cost_per_histo(cfg["theory"], cfg["histos"], counts, P[v], kind)
+        ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v], kind)
+        assert abs(got[v] - ref) <= REL * abs(ref), (v, got[v], ref)
+        np.testing.assert_allclose(ph[v], ref_h, rtol=REL, atol=0)
+
+
+def test_model_values_elementwise(ctx):
+    _say("model values c2 / eq4")
+    cfg, counts = c2()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p = perturbed(cfg["p_true"], 1e-2, 4)
+    got = api.model_eval(ctx, d, th, p)
+    ref = np.concatenate([model.model(cfg["theory"], h, p) for h in cfg["histos"]])
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
+    ps = synth.config_paper_shape(n_bins=4099)
+    hs = [dict(h, first=7, last=4000) for h in ps["histos"][:3]]
+    cnt = counts_for(ps["theory"], hs, ps["p_true"], ps["rng"])
+    th2, d2 = _mk(ctx, ps["theory"], hs, cnt)
+    got = api.model_eval(ctx, d2, th2, ps["p_true"])
+    ref = np.concatenate([model.model(ps["theory"], h, ps["p_true"]) for h in hs])
+    # nu = 13.55 MHz over 10 us: arguments of cos reach ~850 rad
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_c1_gradient_parity(ctx, kind):
+    _say("c1 grad", kind)
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    for seed, rel in ((5, 1e-2), (6, 1e-4)):
+        p = perturbed(cfg["p_true"], rel, seed)
+        c, g = api.chi2_grad(ctx, d, th, p, kind)
+        ref = model.grad(cfg["theory"], cfg["histos"], counts, p, kind)
+        scale = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, p, kind)
+        assert np.all(np.abs(g[0] - ref) <= REL * scale), (g[0], ref)
+        refc = model.cost(cfg["theory"], cfg["histos"], counts, p, kind)
+        assert abs(c[0] - refc) <= REL * refc
+
+
+def test_c1_gradient_vs_finite_differences(ctx):
+    _say("c1 grad vs fd")
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p = perturbed(cfg["p_true"], 1e-2, 7)
+    _, g = api.chi2_grad(ctx, d, th, p)
+    fd = model.grad_fd(cfg["theory"], cfg["histos"], counts, p)
+    scale = np.maximum(np.abs(fd), np.max(np.abs(fd)) * 1e-3)
+    assert np.all(np.abs(g[0] - fd) <= 1e-6 * scale)
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_c2_gradient_parity(ctx, kind):
+    _say("c2 grad", kind)
+    cfg, counts = c2()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p = perturbed(cfg["p_true"], 1e-2, 8)
+    c, g = api.chi2_grad(ctx, d, th, p, kind)
+    ref = model.grad(cfg["theory"], cfg["histos"], counts, p, kind)
+    scale = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, p, kind)
+    assert np.all(np.abs(g[0] - ref) <= REL * scale)
+
+
+def test_c3_vectors_sampled(ctx):
+    """4096 vectors in one launch (the benchmark's launch); 48 sampled vectors
+    checked one by one against the oracle, every vector against a separate
+    single-vector launch."""
+    _say("c3 4096 vectors")
+    cfg, counts = c3()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    P = cfg["P"]
+    got = api.chi2_eval(ctx, d, th, P)
+    cg, gg = api.chi2_grad(ctx, d, th, P)
+    np.testing.assert_array_equal(cg, got)
+    idx = np.random.default_rng(0).choice(P.shape[0], 48, replace=False)
+    for v in idx:
+        ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v])
+        assert abs(got[v] - ref) <= REL * ref
+        one = api.chi2_eval(ctx, d, th, P[v])
+        assert one[0] == got[v]
+    for v in idx[:8]:
+        ref = model.grad(cfg["theory"], cfg["histos"], counts, P[v])
+        scale = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, P[v])
+        assert np.all(np.abs(gg[v] - ref) <= REL * scale)
+
+
+def test_deterministic_and_tile_independent(ctx):
+    _say("determinism / tiles")
+    cfg, counts = c2()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p = perturbed(cfg["p_true"], 1e-3, 9)
+    first = api.chi2_grad(ctx, d, th, p)
+    for _ in range(5):
+        again = api.chi2_grad(ctx, d, th, p)
+        np.testing.assert_array_equal(again[0], first[0])
+        np.testing.assert_array_equal(again[1], first[1])
+    old = ctx.tile
+    try:
+        for tb in (256, 1024, 2048, 8192, 16384, 65536):
+            ctx.tile = tb
+            c, g = api.chi2_grad(ctx, d, th, p)
+            assert abs(c[0] - first[0][0]) <= 1e-13 * first[0][0]
+            assert np.all(np.abs(g - first[1]) <= 1e-12 * np.max(np.abs(first[1])))
+    finally:
+        ctx.tile = old
+
+
+def test_edge_cases(ctx):
+    _say("edge cases")
+    th_d = synth.theory_exp_cos()
+    p = np.array([800.0, 4.0, 0.2, 0.7, 2.3, 0.4])
+    rng = np.random.default_rng(12)
+    histos = [
+        {"n_bins": 1, "dt": 0.01, "t0_bin": 0.0, "first": 0, "last": 0, "map_row": 0},        # one bin
+        {"n_bins": 257, "dt": 0.01, "t0_bin": 0.0, "first": 0, "last": 256, "map_row": 0},    # ragged
+        {"n_bins": 5000, "dt": 0.002, "t0_bin": 13.5, "first": 100, "last": 4321, "map_row": 0},  # t0, range
+        {"n_bins": 3000, "dt": 0.004, "t0_bin": 0.0, "first": 0, "last": 2999, "map_row": 0},
+    ]
+    cnt = counts_for(th_d, histos, p, rng)
+    cnt[3][:] = np.floor(cnt[3] / 200.0)  # many empty bins
+    th, d = _mk(ctx, th_d, histos, cnt)
+    q = perturbed(p, 1e-2, 13)
+    for kind in ("chi2", "poisson"):
+        got, ph = api.chi2_eval(ctx, d, th, q, kind, per_histo=True)
+        ref_h = model.cost_per_histo(th_d, histos, cnt, q, kind)
+        np.testing.assert_allclose(ph[0], ref_h, rtol=REL, atol=1e-300)
+        c, g = api.chi2_grad(ctx, d, th, q, kind)
+        ref = model.grad(th_d, histos, cnt, q, kind)
+        scale = model.grad_abs_scale(th_d, histos, cnt, q, kind)
+        assert np.all(np.abs(g[0] - ref) <= REL * scale)
+    # FP64 storage: non-integer (noiseless) counts
+    hs = [{"n_bins": 700, "dt": 0.01, "t0_bin": 0.0, "first": 0, "last": 699, "map_row": 0}]
+    nz = counts_for(th_d, hs, p, rng, noiseless=True)
+    th2, d2 = _mk(ctx, th_d, hs, nz)
+    assert d2.is_f64
+    c = api.chi2_eval(ctx, d2, th2, p)
+    assert 0.0 <= c[0] <= 1e-20 * float(np.sum(nz[0]))
+    # non-finite parameters give NaN
+    bad = p.copy()
+    bad[3] = np.nan
+    assert math.isnan(api.chi2_eval(ctx, d2, th2, bad)[0])
+    # likelihood with N <= 0 < d is +inf
+    neg = p.copy()
+    neg[0], neg[1] = -100.0, 0.0
+    assert api.chi2_eval(ctx, d2, th2, neg, "poisson")[0] == math.inf
+
+
+def test_primitive_coverage(ctx):
+    """ge with a literal and a free beta, stg, sg and the function-array route."""
+    _say("primitives")
+    rng = np.random.default_rng(14)
+    hs = [{"n_bins": 3000, "dt": 0.003, "t0_bin": 0.0, "first": 0, "last": 2999, "map_row": 0}]
+    g = synth.theory_exp_cos()
+    g["terms"][0]["factors"][0] = {"prim": "ge", "args": [("p", 3), ("p", 6)]}
+    g["map"] = [list(range(7))]
+    g["n_par"] = 7
+    cases = [
+        (g, np.array([900.0, 3.0, 0.2, 0.8, 1.7, 0.3, 1.4])),
+        (synth.theory_gauss_cos(), np.array([900.0, 3.0, 0.2, 0.4, 1.7, 0.3])),
+        (synth.theory_stg(), np.array([900.0, 3.0, 0.2, 0.45])),
+        (synth.theory_exp_gkt(), np.array([900.0, 3.0, 0.15, 0.8, 0.12, 0.4])),
+    ]
+    for th_d, p in cases:
+        cnt = counts_for(th_d, hs, p, rng)
+        th, d = _mk(ctx, th_d, hs, cnt)
+        q = perturbed(p, 1e-2, 15)
+        for kind in ("chi2", "poisson"):
+            c, gr = api.chi2_grad(ctx, d, th, q, kind)
+            ref = model.cost(th_d, hs, cnt, q, kind)
+            assert abs(c[0] - ref) <= REL * ref
+            refg = model.grad(th_d, hs, cnt, q, kind)
+            scale = model.grad_abs_scale(th_d, hs, cnt, q, kind)
+            assert np.all(np.abs(gr[0] - refg) <= REL * scale), (th_d["names"], gr[0], refg)
+    ps = synth.config_paper_shape(n_bins=6000)
+    hs = ps["histos"][:4]
+    cnt = counts_for(ps["theory"], hs, ps["p_true"], ps["rng"])
+    th, d = _mk(ctx, ps["theory"], hs, cnt)
+    q = perturbed(ps["p_true"], 1e-3, 16)
+    c, gr = api.chi2_grad(ctx, d, th, q)
+    assert abs(c[0] - model.cost(ps["theory"], hs, cnt, q)) <= REL * c[0]
+    refg = model.grad(ps["theory"], hs, cnt, q)
+    scale = model.grad_abs_scale(ps["theory"], hs, cnt, q)
+    assert np.all(np.abs(gr[0] - refg) <= REL * scale)
+
+
+def test_batch_uneven_datasets(ctx):
+    """Independent datasets of uneven sizes and different theories in one launch."""
+    _say("batch uneven")
+    cfg = synth.config_c4(n_sets=24, lo_exp=8, hi_exp=14)
+    rng = cfg["rng"]
+    sets = cfg["sets"]
+    cnts = [counts_for(s["theory"], s["histos"], s["p_true"], rng) for s in sets]
+    ths = [api.Theory(ctx, s["theory"]) for s in sets]
+    ds = [api.Data(ctx, s["histos"], c) for s, c in zip(sets, cnts)]
+    ld = 6
+    P = np.zeros((len(sets), ld))
+    for j, s in enumerate(sets):
+        P[j, :s["start"].size] = s["start"]
+    for kind in ("chi2", "poisson"):
+        c, g = api.chi2_batch(ctx, ds, ths, P, kind, grad=True)
+        c_only = api.chi2_batch(ctx, ds, ths, P, kind)
+        np.testing.assert_array_equal(c, c_only)
+        for j, s in enumerate(sets):
+            n = s["start"].size
+            ref = model.cost(s["theory"], s["histos"], cnts[j], s["start"], kind)
+            assert abs(c[j] - ref) <= REL * ref, (j, s["family"])
+            refg = model.grad(s["theory"], s["histos"], cnts[j], s["start"], kind)
+            scale = model.grad_abs_scale(s["theory"], s["histos"], cnts[j], s["start"], kind)
+            assert np.all(np.abs(g[j, :n] - refg) <= REL * scale), (j, s["family"])
+            one = api.chi2_eval(ctx, ds[j], ths[j], s["start"], kind)
+            assert one[0] == c[j]
+
+
+def test_torch_device_path_and_autograd(ctx):
+    import torch
+    _say("torch + autograd")
+    from paper_1604_02334_amd import Chi2
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p = torch.tensor(perturbed(cfg["p_true"], 1e-2, 17), dtype=torch.float64, device="cuda", requires_grad=True)
+    c = Chi2.apply(p, ctx, d, th, "chi2")
+    (2.0 * c).backward()
+    torch.cuda.synchronize()
+    ref = model.grad(cfg["theory"], cfg["histos"], counts, p.detach().cpu().numpy())
+    scale = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, p.detach().cpu().numpy())
+    assert np.all(np.abs(p.grad.cpu().numpy() - 2.0 * ref) <= 2 * REL * scale)
+    host = api.chi2_eval(ctx, d, th, p.detach().cpu().numpy())
+    assert c.item() == host[0]
+
+
+def test_specialised_kernels_match_generic_and_direct(ctx):
+    """Each compiled shape against the generic interpreted kernel, and the
+    recurrence path (anchor every 64 steps) against direct evaluation of every
+    bin (anchor every step)."""
+    _say("shapes vs generic, anchors")
+    rng = np.random.default_rng(21)
+    hs = [{"n_bins": 20000, "dt": 0.0005, "t0_bin": 0.0, "first": 3, "last": 19990, "map_row": 0}]
+    cases = [(synth.theory_exp_cos(), np.array([900.0, 3.0, 0.2, 0.8, 7.7, 0.3])),
+             (synth.theory_gauss_cos(), np.array([900.0, 3.0, 0.2, 0.9, 7.7, 0.3])),
+             (synth.theory_stg(), np.array([900.0, 3.0, 0.2, 0.95])),
+             (synth.theory_exp_gkt(), np.array([900.0, 3.0, 0.15, 0.8, 0.12, 0.4]))]
+    c2cfg, c2counts = c2()
+    for th_d, p in cases + [(c2cfg["theory"], c2cfg["p_true"])]:
+        if th_d is c2cfg["theory"]:
+            hh, cnt = c2cfg["histos"], c2counts
+        else:
+            hh, cnt = hs, counts_for(th_d, hs, p, rng)
+        th, d = _mk(ctx, th_d, hh, cnt)
+        q = perturbed(p, 1e-2, 22)
+        for kind in ("chi2", "poisson"):
+            ref_c, ref_g = api.chi2_grad(ctx, d, th, q, kind)
+            gscale = np.max(np.abs(ref_g))
+            try:
+                ctx.set_specialize(False)
+                c, g = api.chi2_grad(ctx, d, th, q, kind)
+                assert abs(c[0] - ref_c[0]) <= 1e-13 * ref_c[0]
+                assert np.all(np.abs(g - ref_g) <= 1e-11 * gscale)
+                ctx.set_specialize(True)
+                ctx.anchor = 1
+                c, g = api.chi2_grad(ctx, d, th, q, kind)
+                assert abs(c[0] - ref_c[0]) <= 1e-12 * ref_c[0], (th_d["names"], kind, c[0], ref_c[0])
+                assert np.all(np.abs(g - ref_g) <= 1e-10 * gscale)
+            finally:
+                ctx.set_specialize(True)
+                ctx.anchor = 0

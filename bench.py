@@ -133,6 +133,9 @@ def main():
             ev[1].record(st)
         return c
 
+    # measured tile / anchor choice for both launches (untimed)
+    tune_eval = api.autotune(ctx, data, th, s_dev)
+    tune_grad = api.autotune(ctx, data, th, p_dev, grad=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -182,6 +185,8 @@ def main():
                      "kernel": "eval_kernel<chi2, cost, float>", "kernel_ms": round(k_ms, 5),
                      "flops_per_bin": FLOPS_PER_BIN_CHI2, "bins_per_launch": k_bins},
         "extra": {"stencil_kernel_gbin_s": round(k_bins / (k_ms * 1e-3) / 1e9, 2),
+                  "tuned_stencil": {"tile": tune_eval[0], "anchor": tune_eval[1]},
+                  "tuned_grad": {"tile": tune_grad[0], "anchor": tune_grad[1]},
                   "single_eval_host_latency_us": round(lat_us, 2)},
     }
     if not args.no_cpu:

@@ -202,15 +202,19 @@ mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
                         const double *params, unsigned mem, double *out);
 
 /* Tile size (bins per workgroup) used by evaluation launches on this
- * context: 0 restores the tuned default.  Must be a multiple of 256 in
- * [256, 65536]; results do not depend on it beyond rounding order. */
+ * context.  0 (default): per launch, the choice mu_autotune measured for the
+ * same theory shape, mode, cost and size (to a power of two), else about four
+ * workgroups per compute unit with tiles of 1024 .. 65536 bins.  Otherwise a
+ * multiple of 256 in [256, 65536].  Results depend on it only through the
+ * rounding order of the sums. */
 mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins);
 int32_t mu_ctx_get_tile(const mu_ctx *ctx);
 
 /* Lane steps between exact re-evaluations of the theory's factors (the rest
  * are advanced by exact recurrences of the uniform time grid): 1 evaluates
- * every bin directly; 0 restores the default (64).  Range [1, 64]; the
- * recurrence drift stays below ~5e-13 relative at 64. */
+ * every bin directly; 0 restores the default (64).  Range [1, 256]; the
+ * recurrence drift of a factor grows like k eps (geometric, rotation) and
+ * k^2 eps / 2 (Gaussian): below 5e-13 relative at 64 and 8e-12 at 256. */
 mu_status mu_ctx_set_anchor(mu_ctx *ctx, int32_t every);
 int32_t mu_ctx_get_anchor(const mu_ctx *ctx);
 
@@ -219,6 +223,59 @@ int32_t mu_ctx_get_anchor(const mu_ctx *ctx);
  * kernel; 0: every theory runs the generic interpreted kernel.  Results agree
  * to rounding either way. */
 mu_status mu_ctx_set_specialize(mu_ctx *ctx, int32_t on);
+
+/* Measure the evaluation of n_vec vectors over `data` (cost, or cost and
+ * gradient when grad != 0) for tile sizes 1024 .. 65536 and anchor intervals
+ * 32 .. 256, keep candidates whose costs agree with the first to 1e-12
+ * relative, and remember the fastest for later launches of the same theory
+ * shape, mode, cost and size (to a power of two) while the tile size is 0.
+ * Writes the choice and its time per launch in microseconds (any may be
+ * NULL).  Leaves the explicit tile size and anchor interval unchanged. */
+mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                      const double *params, int32_t n_vec, unsigned mem, int32_t grad,
+                      int32_t *best_tile, int32_t *best_anchor, double *best_us);
+
+/* ----------------------------------------------------------------- fitting */
+
+/* Options of mu_fit_batch (zero-initialise, then set what you need). */
+typedef struct {
+  int32_t max_fcn;        /* cost evaluations per fit (0: 100000) */
+  int32_t max_iter;       /* line-search iterations per fit (0: 1000) */
+  double tol_edm;         /* stop the variable-metric stage when g^T V g / 2 < tol_edm (0: 1e-8) */
+  double tol_step_rel;    /* ... or when every step is below tol * max(|p_k|, sigma_k) (0: 1e-7) */
+  int32_t analytic_grad;  /* 1: gradients from the adjoint kernel; 0: central differences (2n costs) */
+  int32_t batched;        /* 1: every round evaluates the requests of all active fits in one launch;
+                             0: fits one after another, one launch per evaluated point */
+  int32_t polish;         /* 1: finish with Newton steps on a Hessian from central differences of the
+                             gradient until the relative step is below 1e-12 */
+  int32_t reserved;
+  const uint8_t *fixed;   /* [n_fits][ld]: non-zero entries are held at their start values; may be NULL */
+} mu_fit_opts;
+
+typedef struct {
+  double cost;     /* cost at params_out */
+  double edm;      /* estimated distance to the minimum, g^T V g / 2 */
+  int32_t n_iter;  /* accepted variable-metric steps */
+  int32_t n_fcn;   /* cost evaluations (gradient stencil points included) */
+  int32_t n_grad;  /* gradient evaluations */
+  int32_t status;  /* 0 converged, 1 evaluation or iteration budget spent, 2 non-finite cost at the start,
+                      3 line search failed (params_out is the best point found) */
+} mu_fit_result;
+
+/* Minimise the cost of n_fits independent fits (Sec. 4: the fit of P by
+ * minimising Eq. 2 or Eq. 3; there with Minuit2's variable-metric method).
+ * Fit f uses data[f], th[f] and start[f][0 .. n_par-1] (row stride ld >= every
+ * theory's n_par).  Method: start Hessian by central differences of the
+ * gradient, BFGS updates of the inverse Hessian V with a backtracking line
+ * search along -V g, and optionally a final Newton polish.  Outputs:
+ * params_out [n_fits][ld] (entries past n_par copied from start), cov_out
+ * [n_fits][ld][ld] = 2 V (chi^2 and likelihood are -2 ln L up to a constant;
+ * zero rows for fixed parameters; may be NULL), res [n_fits].  MU_E_ARG for a
+ * non-finite start value.  A fit whose cost is not finite at its start ends
+ * with status 2; this is not an error of the call. */
+mu_status mu_fit_batch(mu_ctx *ctx, int32_t n_fits, const mu_data *const *data, const mu_theory *const *th,
+                       mu_cost cost_kind, int32_t ld, const double *start, const mu_fit_opts *opts,
+                       double *params_out, double *cov_out, mu_fit_result *res);
 
 #ifdef __cplusplus
 }

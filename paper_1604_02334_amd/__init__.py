@@ -12,9 +12,11 @@ from .api import (  # noqa: F401
     Context,
     Data,
     Theory,
+    autotune,
     chi2_batch,
     chi2_eval,
     chi2_grad,
+    fit_batch,
     histo_check,
     model_eval,
     theory_check,

@@ -60,6 +60,17 @@ class mu_theory_desc(C.Structure):
                 ("F", dp), ("f0", dp), ("n_fun", C.c_int32), ("n_par", C.c_int32)]
 
 
+class mu_fit_opts(C.Structure):
+    _fields_ = [("max_fcn", C.c_int32), ("max_iter", C.c_int32), ("tol_edm", C.c_double),
+                ("tol_step_rel", C.c_double), ("analytic_grad", C.c_int32), ("batched", C.c_int32),
+                ("polish", C.c_int32), ("reserved", C.c_int32), ("fixed", C.c_void_p)]
+
+
+class mu_fit_result(C.Structure):
+    _fields_ = [("cost", C.c_double), ("edm", C.c_double), ("n_iter", C.c_int32), ("n_fcn", C.c_int32),
+                ("n_grad", C.c_int32), ("status", C.c_int32)]
+
+
 _lib = None
 
 
@@ -89,6 +100,8 @@ def lib():
         "mu_ctx_set_anchor": (S, [vp, C.c_int32]),
         "mu_ctx_get_anchor": (C.c_int32, [vp]),
         "mu_ctx_set_specialize": (S, [vp, C.c_int32]),
+        "mu_autotune": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, C.c_int32, C.POINTER(C.c_int32),
+                            C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mu_histo_check": (S, [C.POINTER(mu_histo), C.c_int32, C.c_char_p, C.c_int32]),
         "mu_data_create": (S, [vp, C.POINTER(mu_histo), C.c_int32, C.POINTER(vp)]),
         "mu_data_destroy": (S, [vp]),
@@ -103,6 +116,8 @@ def lib():
         "mu_chi2_grad": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, vp, vp]),
         "mu_chi2_batch": (S, [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), S, C.c_int32, vp, C.c_uint, vp, vp]),
         "mu_model_eval": (S, [vp, vp, vp, vp, C.c_uint, vp]),
+        "mu_fit_batch": (S, [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), S, C.c_int32, vp,
+                             C.POINTER(mu_fit_opts), vp, vp, C.POINTER(mu_fit_result)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -116,7 +131,7 @@ def exported_symbols():
     """Names declared in include/mu.h that the binding expects."""
     return sorted(["mu_abi_version", "mu_status_string", "mu_ctx_create", "mu_ctx_destroy", "mu_ctx_last_error",
                    "mu_ctx_synchronize", "mu_ctx_set_tile", "mu_ctx_get_tile", "mu_ctx_set_anchor", "mu_ctx_get_anchor",
-                   "mu_ctx_set_specialize", "mu_histo_check", "mu_data_create",
+                   "mu_ctx_set_specialize", "mu_autotune", "mu_histo_check", "mu_data_create",
                    "mu_data_destroy", "mu_data_bins", "mu_data_histos", "mu_data_is_f64", "mu_theory_check",
                    "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_chi2_eval", "mu_chi2_grad",
-                   "mu_chi2_batch", "mu_model_eval"])
+                   "mu_chi2_batch", "mu_model_eval", "mu_fit_batch"])

@@ -335,3 +335,59 @@ def model_eval(ctx, data, theory, params):
     _check(L.mu_model_eval(ctx.h, data.h, theory.h, p.ctypes.data, A.MU_MEM_HOST, out.ctypes.data), ctx.h,
            "mu_model_eval")
     return out
+
+
+def autotune(ctx, data, theory, params, cost="chi2", grad=False):
+    """Measure tile / anchor candidates for this workload and remember the
+    fastest in the context.  Returns (tile, anchor, microseconds per launch)."""
+    L = A.lib()
+    bt, ba, us = C.c_int32(), C.c_int32(), C.c_double()
+    if _is_torch(params) and params.is_cuda:
+        import torch
+        p = params.detach().to(torch.float64).contiguous()
+        if p.dim() == 1:
+            p = p[None]
+        cur = ctx._enter_device()
+        _check(L.mu_autotune(ctx.h, data.h, theory.h, _cost_code(cost), C.c_void_p(p.data_ptr()), p.shape[0],
+                             A.MU_MEM_DEVICE, 1 if grad else 0, C.byref(bt), C.byref(ba), C.byref(us)),
+               ctx.h, "mu_autotune")
+        ctx._leave_device(cur, [p])
+    else:
+        p = _as_host_params(params, theory.n_par)
+        _check(L.mu_autotune(ctx.h, data.h, theory.h, _cost_code(cost), p.ctypes.data, p.shape[0], A.MU_MEM_HOST,
+                             1 if grad else 0, C.byref(bt), C.byref(ba), C.byref(us)), ctx.h, "mu_autotune")
+    return bt.value, ba.value, us.value
+
+
+def fit_batch(ctx, datas, theories, start, cost="chi2", fixed=None, analytic_grad=True, batched=True,
+              polish=True, max_fcn=0, max_iter=0, tol_edm=0.0, tol_step_rel=0.0, want_cov=True):
+    """Minimise n_fits independent fits (host arrays).  start: [n_fits, ld].
+    Returns (params [n_fits, ld], cov [n_fits, ld, ld] or None, list of result dicts)."""
+    L = A.lib()
+    n = len(datas)
+    if len(theories) != n:
+        raise ValueError("need one theory per dataset")
+    s = np.ascontiguousarray(np.asarray(start, dtype=np.float64))
+    if s.ndim == 1:
+        s = s[None]
+    if s.shape[0] != n:
+        raise ValueError("start must have shape [n_fits, ld]")
+    ld = s.shape[1]
+    o = A.mu_fit_opts()
+    o.max_fcn, o.max_iter = int(max_fcn), int(max_iter)
+    o.tol_edm, o.tol_step_rel = float(tol_edm), float(tol_step_rel)
+    o.analytic_grad, o.batched, o.polish = int(bool(analytic_grad)), int(bool(batched)), int(bool(polish))
+    fx = None
+    if fixed is not None:
+        fx = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed, dtype=np.uint8), (n, ld)))
+        o.fixed = fx.ctypes.data
+    out = np.empty((n, ld))
+    cov = np.empty((n, ld, ld)) if want_cov else None
+    res = (A.mu_fit_result * n)()
+    dh = (C.c_void_p * n)(*[d.h.value for d in datas])
+    th = (C.c_void_p * n)(*[t.h.value for t in theories])
+    _check(L.mu_fit_batch(ctx.h, n, dh, th, _cost_code(cost), ld, s.ctypes.data, C.byref(o), out.ctypes.data,
+                          cov.ctypes.data if want_cov else None, res), ctx.h, "mu_fit_batch")
+    rs = [{"cost": r.cost, "edm": r.edm, "n_iter": r.n_iter, "n_fcn": r.n_fcn, "n_grad": r.n_grad,
+           "status": r.status} for r in res]
+    return out, cov, rs

@@ -195,7 +195,7 @@ extern "C" mu_status mu_ctx_synchronize(mu_ctx *ctx) {
 extern "C" mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins) {
   if (!ctx) return MU_E_ARG;
   if (tile_bins == 0) {
-    ctx->tile_bins = kDefaultTile;
+    ctx->tile_bins = 0;
     return MU_OK;
   }
   if (tile_bins < kBlock || tile_bins > 65536 || tile_bins % kBlock) {
@@ -214,8 +214,8 @@ extern "C" mu_status mu_ctx_set_anchor(mu_ctx *ctx, int32_t every) {
     ctx->anchor_every = kDefaultAnchor;
     return MU_OK;
   }
-  if (every < 1 || every > 64) {
-    set_err(ctx, "anchor interval must be in [1, 64] lane steps");
+  if (every < 1 || every > 256) {
+    set_err(ctx, "anchor interval must be in [1, 256] lane steps");
     return MU_E_ARG;
   }
   ctx->anchor_every = every;
@@ -288,16 +288,21 @@ extern "C" mu_status mu_histo_check(const mu_histo *h, int32_t n_histo, char *ms
   return s;
 }
 
-mu_status mu_data::build_tiles(int tile_bins) {
-  if (tile_bins == tiles_for) return MU_OK;
+mu_status mu_data::tiles(int tile_bins, const TileSet **out) {
+  for (const TileSet &t : sets)
+    if (t.tile_bins == tile_bins) {
+      *out = &t;
+      return MU_OK;
+    }
   std::vector<DevTile> tl;
+  std::vector<DevHisto> h2 = hh;
   for (int j = 0; j < n_histo; ++j) {
-    hh[j].tile0 = (int32_t)tl.size();
-    for (int64_t b = 0; b < hh[j].n; b += tile_bins) {
+    h2[j].tile0 = (int32_t)tl.size();
+    for (int64_t b = 0; b < h2[j].n; b += tile_bins) {
       DevTile t;
       t.begin = b;
       t.histo = j;
-      t.n = (int32_t)std::min<int64_t>(tile_bins, hh[j].n - b);
+      t.n = (int32_t)std::min<int64_t>(tile_bins, h2[j].n - b);
       tl.push_back(t);
     }
   }
@@ -305,18 +310,53 @@ mu_status mu_data::build_tiles(int tile_bins) {
     set_err(ctx, "dataset needs too many tiles");
     return MU_E_UNSUPPORTED;
   }
-  hipStreamSynchronize(ctx->stream);  // earlier launches may still read the old tables
-  if (d_tiles) hipFree(d_tiles);
-  d_tiles = nullptr;
-  hipError_t e = hipMalloc(&d_tiles, tl.size() * sizeof(DevTile));
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(tiles)");
-  e = hipMemcpy(d_tiles, tl.data(), tl.size() * sizeof(DevTile), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(tiles)");
-  e = hipMemcpy(d_histos, hh.data(), hh.size() * sizeof(DevHisto), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(histos)");
-  n_tiles = (int32_t)tl.size();
-  tiles_for = tile_bins;
+  TileSet ts;
+  ts.tile_bins = tile_bins;
+  ts.n_tiles = (int32_t)tl.size();
+  hipError_t e = hipMalloc(&ts.d_tiles, tl.size() * sizeof(DevTile));
+  if (e == hipSuccess) e = hipMalloc(&ts.d_histos, h2.size() * sizeof(DevHisto));
+  if (e == hipSuccess) e = hipMemcpy(ts.d_tiles, tl.data(), tl.size() * sizeof(DevTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ts.d_histos, h2.data(), h2.size() * sizeof(DevHisto), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (ts.d_tiles) hipFree(ts.d_tiles);
+    if (ts.d_histos) hipFree(ts.d_histos);
+    return hip_fail(ctx, e, "tile tables");
+  }
+  sets.push_back(ts);
+  *out = &sets.back();
   return MU_OK;
+}
+
+void mu_data::free_dev() {
+  if (counts) hipFree(counts);
+  counts = nullptr;
+  for (TileSet &t : sets) {
+    if (t.d_tiles) hipFree(t.d_tiles);
+    if (t.d_histos) hipFree(t.d_histos);
+  }
+  sets.clear();
+}
+
+// Tile size for a launch: the tuned choice for this (shape, mode, cost, size)
+// if one was measured, else about four workgroups per compute unit with
+// tiles of 1024 .. 65536 bins.
+int mu_ctx::pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const {
+  *anchor = anchor_every;
+  if (tile_bins > 0) return tile_bins;
+  int lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= work) ++lg;
+  const int key = ((shape * 4 + mode) * 2 + cost) * 64 + lg;
+  for (const Tuned &t : tuned)
+    if (t.key == key) {
+      *anchor = t.anchor;
+      return t.tile;
+    }
+  int64_t want = work / (4 * std::max(n_cu, 1));
+  int tile = kMinTile;
+  while (tile < kMaxTile && (int64_t)tile * 2 <= want) tile *= 2;
+  // no tile longer than the longest histogram needs
+  while (tile > kMinTile && (int64_t)tile / 2 >= longest) tile /= 2;
+  return tile;
 }
 
 extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_histo, mu_data **out) {
@@ -346,6 +386,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
     x.map_row = h[j].map_row;
     x.tile0 = 0;
     d->max_row = std::max(d->max_row, (int)h[j].map_row);
+    d->longest = std::max(d->longest, x.n);
     total += x.n;
   }
   d->total = total;
@@ -354,12 +395,6 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
   if (e != hipSuccess) {
     delete d;
     set_err(ctx, "device allocation for %lld bins failed", (long long)total);
-    return MU_E_NOMEM;
-  }
-  e = hipMalloc(&d->d_histos, n_histo * sizeof(DevHisto));
-  if (e != hipSuccess) {
-    hipFree(d->counts);
-    delete d;
     return MU_E_NOMEM;
   }
   // pack on the host, upload once
@@ -378,18 +413,9 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
     e = hipMemcpy(d->counts, buf.data(), buf.size(), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
-    hipFree(d->counts);
-    hipFree(d->d_histos);
+    d->free_dev();
     delete d;
     return hip_fail(ctx, e, "hipMemcpy(counts)");
-  }
-  st = d->build_tiles(ctx->tile_bins);
-  if (st != MU_OK) {
-    hipFree(d->counts);
-    hipFree(d->d_histos);
-    if (d->d_tiles) hipFree(d->d_tiles);
-    delete d;
-    return st;
   }
   ctx->children++;
   *out = d;
@@ -400,9 +426,7 @@ extern "C" mu_status mu_data_destroy(mu_data *d) {
   if (!d) return MU_E_ARG;
   hipSetDevice(d->ctx->device);
   hipStreamSynchronize(d->ctx->stream);
-  hipFree(d->counts);
-  hipFree(d->d_histos);
-  if (d->d_tiles) hipFree(d->d_tiles);
+  d->free_dev();
   d->ctx->children--;
   delete d;
   return MU_OK;
@@ -691,7 +715,7 @@ mu_status check_pair(mu_ctx *ctx, const mu_data *d, const mu_theory *th) {
 
 }  // namespace mu
 
-namespace {
+namespace mu {
 
 // Evaluate n_vec vectors over one dataset in one launch.  mode: cost, grad, model.
 mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *params,
@@ -711,9 +735,13 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   }
   mu_status st;
   hipSetDevice(ctx->device);
-  if ((st = d->build_tiles(ctx->tile_bins)) != MU_OK) return st;
+  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
+  int anchor = ctx->anchor_every;
+  const int tile = ctx->pick_tile(shape, mode, cost_kind, (int64_t)n_vec * d->total, d->longest, &anchor);
+  const TileSet *ts = nullptr;
+  if ((st = d->tiles(tile, &ts)) != MU_OK) return st;
   const int n_par = th->h.n_par;
-  const int64_t n_blocks = (int64_t)n_vec * d->n_tiles;
+  const int64_t n_blocks = (int64_t)n_vec * ts->n_tiles;
   if (n_blocks > INT32_MAX) {
     set_err(ctx, "launch needs more than 2^31 workgroups");
     return MU_E_UNSUPPORTED;
@@ -749,15 +777,15 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.tmpl.th = th->d_th;
-  a.tmpl.histos = d->d_histos;
+  a.tmpl.histos = ts->d_histos;
   a.tmpl.counts = d->counts;
-  a.tmpl.tiles = d->d_tiles;
+  a.tmpl.tiles = ts->d_tiles;
   a.tmpl.p = dp;
   a.tmpl.cost_out = dc;
   a.tmpl.histo_out = dh;
   a.tmpl.grad_out = dg;
   a.tmpl.model_out = dm;
-  a.tmpl.n_tiles = d->n_tiles;
+  a.tmpl.n_tiles = ts->n_tiles;
   a.tmpl.n_histo = d->n_histo;
   a.p_stride = n_par;
   a.grad_stride = n_par;
@@ -766,9 +794,9 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   a.block_job = nullptr;
   a.n_blocks = (int32_t)n_blocks;
   a.cost_kind = cost_kind;
-  a.anchor_every = ctx->anchor_every;
+  a.anchor_every = anchor;
   a.partial = static_cast<double *>(ctx->partial.ptr);
-  e = launch_eval(a, mode, d->f64, ctx->specialize ? th->shape : kShapeGeneric, ctx->stream);
+  e = launch_eval(a, mode, d->f64, shape, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
   if (mode != kModeModel) {
     e = launch_merge(a, mode, n_vec, ctx->stream);
@@ -790,7 +818,7 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   return MU_OK;
 }
 
-}  // namespace
+}  // namespace mu
 
 extern "C" mu_status mu_chi2_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
                                   const double *params, int32_t n_vec, unsigned mem, double *cost,
@@ -863,23 +891,31 @@ extern "C" mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *c
     }
   }
   hipSetDevice(ctx->device);
+  int64_t work = 0, longest = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    work += data[j]->total;
+    longest = std::max(longest, data[j]->longest);
+  }
+  int anchor = ctx->anchor_every;
+  const int tile = ctx->pick_tile(kShapeGeneric, grad ? kModeGrad : kModeCost, cost_kind, work, longest, &anchor);
+  std::vector<const TileSet *> sets(n_jobs);
   int64_t n_blocks = 0;
   for (int j = 0; j < n_jobs; ++j) {
-    if ((st = const_cast<mu_data *>(data[j])->build_tiles(ctx->tile_bins)) != MU_OK) return st;
-    n_blocks += data[j]->n_tiles;
+    if ((st = const_cast<mu_data *>(data[j])->tiles(tile, &sets[j])) != MU_OK) return st;
+    n_blocks += sets[j]->n_tiles;
   }
   if (n_blocks > INT32_MAX) {
     set_err(ctx, "launch needs more than 2^31 workgroups");
     return MU_E_UNSUPPORTED;
   }
-  return run_batch(ctx, n_jobs, data, th, cost_kind, ld, params, mem, cost, grad, n_blocks);
+  return run_batch(ctx, n_jobs, data, sets.data(), th, cost_kind, ld, params, mem, cost, grad, n_blocks, anchor);
 }
 
 namespace mu {
 
-mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,
-                    int cost_kind, int32_t ld, const double *params, unsigned mem, double *cost, double *grad,
-                    int64_t n_blocks) {
+mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
+                    const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
+                    double *cost, double *grad, int64_t n_blocks, int anchor) {
   mu_status st;
   hipError_t e;
   const size_t n_p = (size_t)n_jobs * ld;
@@ -918,15 +954,15 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     DevJob &J = jobs[j];
     std::memset(&J, 0, sizeof J);
     J.th = th[j]->d_th;
-    J.histos = data[j]->d_histos;
+    J.histos = sets[j]->d_histos;
     J.counts = data[j]->counts;
-    J.tiles = data[j]->d_tiles;
+    J.tiles = sets[j]->d_tiles;
     J.p = dp + (size_t)j * ld;
     J.cost_out = dc + j;
     J.histo_out = nullptr;
     J.grad_out = dg ? dg + (size_t)j * ld : nullptr;
     J.model_out = nullptr;
-    J.n_tiles = data[j]->n_tiles;
+    J.n_tiles = sets[j]->n_tiles;
     J.n_histo = data[j]->n_histo;
     J.tile_base = slot_base;
     slot_base += J.n_tiles;
@@ -986,3 +1022,101 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
 }
 
 }  // namespace mu
+
+// ------------------------------------------------------------------ tuning
+
+extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                                 const double *params, int32_t n_vec, unsigned mem, int32_t grad,
+                                 int32_t *best_tile, int32_t *best_anchor, double *best_us) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (!params || n_vec < 1 || (mem != MU_MEM_HOST && mem != MU_MEM_DEVICE) ||
+      (cost_kind != MU_COST_CHI2 && cost_kind != MU_COST_POISSON)) {
+    set_err(ctx, "autotune needs parameters, n_vec >= 1, a memory kind and a cost kind");
+    return MU_E_ARG;
+  }
+  hipSetDevice(ctx->device);
+  mu_data *d = const_cast<mu_data *>(data);
+  const int n_par = th->h.n_par;
+  const int mode = grad ? kModeGrad : kModeCost;
+  double *buf = nullptr;
+  const size_t n_p = (size_t)n_vec * n_par;
+  const size_t n_out = (size_t)n_vec * (1 + (grad ? n_par : 0));
+  hipError_t e = hipMalloc(&buf, (n_p + n_out) * sizeof(double));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(autotune)");
+  e = hipMemcpyAsync(buf, params, n_p * sizeof(double),
+                     mem == MU_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream);
+  double *dc = buf + n_p, *dg = grad ? dc + n_vec : nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const int saved_tile = ctx->tile_bins, saved_anchor = ctx->anchor_every;
+  std::vector<double> ref(n_vec), cur(n_vec);
+  bool have_ref = false;
+  int bt = 0, ba = 0;
+  float best = 1e30f;
+  for (int tile = kMinTile; tile <= kMaxTile && st == MU_OK; tile *= 2) {
+    if (tile / 2 >= d->longest && tile > kMinTile) break;
+    for (int anchor : {32, 64, 128, 256}) {
+      ctx->tile_bins = tile;
+      ctx->anchor_every = anchor;
+      for (int w = 0; w < 2 && st == MU_OK; ++w)
+        st = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
+      if (st != MU_OK) break;
+      hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < 5 && st == MU_OK; ++r)
+        st = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
+      hipEventRecord(e1, ctx->stream);
+      if (st != MU_OK) break;
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      // every candidate must reproduce the first one's costs to rounding
+      hipMemcpy(cur.data(), dc, n_vec * sizeof(double), hipMemcpyDeviceToHost);
+      bool ok = true;
+      if (!have_ref) {
+        ref = cur;
+        have_ref = true;
+      } else {
+        for (int v = 0; v < n_vec; ++v)
+          if (!(std::fabs(cur[v] - ref[v]) <= 1e-12 * std::fabs(ref[v])) && !(std::isnan(cur[v]) && std::isnan(ref[v])))
+            ok = false;
+      }
+      if (ok && ms < best) {
+        best = ms;
+        bt = tile;
+        ba = anchor;
+      }
+    }
+  }
+  ctx->tile_bins = saved_tile;
+  ctx->anchor_every = saved_anchor;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamSynchronize(ctx->stream);
+  hipFree(buf);
+  if (st != MU_OK) return st;
+  if (bt == 0) {
+    set_err(ctx, "no tuning candidate ran");
+    return MU_E_DEVICE;
+  }
+  // remember the choice for launches of this shape, mode, cost and size
+  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
+  const int64_t work = (int64_t)n_vec * d->total;
+  int lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= work) ++lg;
+  const int key = ((shape * 4 + mode) * 2 + cost_kind) * 64 + lg;
+  bool found = false;
+  for (auto &t : ctx->tuned)
+    if (t.key == key) {
+      t.tile = bt;
+      t.anchor = ba;
+      found = true;
+    }
+  if (!found) ctx->tuned.push_back({key, bt, ba});
+  if (best_tile) *best_tile = bt;
+  if (best_anchor) *best_anchor = ba;
+  if (best_us) *best_us = best / 5.0 * 1e3;
+  return MU_OK;
+}

@@ -285,10 +285,11 @@ __device__ __forceinline__ double value_grad(int kind, double t, double a0, doub
 }
 
 // Per-bin cost term (Eq. 2 / Eq. 3) and its derivative in N.
-template <int COST, bool WANT_DN>
+template <int COST, bool WANT_DN, bool INT_DATA>
 __device__ __forceinline__ double cost_term(double d, double N, double &dN) {
   if (COST == MU_COST_CHI2) {
-    const double v = d > 0.0 ? d : 1.0;
+    // variance d, or 1 for an empty bin; integer counts: max(d, 1) is the same
+    const double v = INT_DATA ? fmax(d, 1.0) : (d > 0.0 ? d : 1.0);
     // 1/v: hardware reciprocal refined by one Newton step (< 1 ulp + rounding)
     double iv = __builtin_amdgcn_rcp(v);
     iv = fma(iv, fma(-v, iv, 1.0), iv);
@@ -362,9 +363,13 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
 
   if constexpr (MODE == kModeGrad) {
     // chain rule through the map / function array:
-    //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's tiles
+    //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's tiles.
+    // For a chunk of histograms the sums and the map lookups are staged in LDS
+    // (pidx >= 0: parameter index; <= -2: function -(2 + i); -1: no parameter),
+    // then thread k scans them in a fixed order.
     constexpr int HC = 32;
     __shared__ double gR[HC][kRS];
+    __shared__ int pidx[HC][kRS];
     __shared__ double acc_s[MU_MAX_PAR];
     __shared__ double acc_c[MU_MAX_PAR];
     const DevTheory *th = J.th;
@@ -379,28 +384,31 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
       for (int w = tid; w < nh * kRS; w += kBlock) {
         const int hh = w / kRS, r = w % kRS;
         const int h = h0 + hh;
+        const DevRef ref = th->rref[r];
         double s = 0.0;
-        if (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN) {
+        int pi = -1;
+        if (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN) {
           const int k0 = J.histos[h].tile0;
           const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
           Pair q{0.0, 0.0};
           for (int k = k0; k < k1; ++k) q = pair_add(q, Pair{P[k * kSlot + 2 + r], 0.0});
           s = pair_value(q);
+          const int m = th->map[J.histos[h].map_row * th->n_slots + ref.slot];
+          pi = ref.kind == MU_REF_PAR ? m : -(2 + m);
         }
         gR[hh][r] = s;
+        pidx[hh][r] = pi;
       }
       __syncthreads();
       for (int k = tid; k < n_par; k += kBlock) {
         Pair q{acc_s[k], acc_c[k]};
         for (int hh = 0; hh < nh; ++hh) {
-          const int row = J.histos[h0 + hh].map_row;
           for (int r = 0; r < kRS; ++r) {
-            const DevRef ref = th->rref[r];
-            if (ref.kind == MU_REF_PAR) {
-              if (th->map[row * th->n_slots + ref.slot] == k) q = pair_add(q, Pair{gR[hh][r], 0.0});
-            } else if (ref.kind == MU_REF_FUN) {
-              const int i = th->map[row * th->n_slots + ref.slot];
-              q = pair_add(q, Pair{gR[hh][r] * th->F[(int64_t)i * n_par + k], 0.0});
+            const int pi = pidx[hh][r];
+            if (pi == k) {
+              q = pair_add(q, Pair{gR[hh][r], 0.0});
+            } else if (pi <= -2) {
+              q = pair_add(q, Pair{gR[hh][r] * th->F[(int64_t)(-2 - pi) * n_par + k], 0.0});
             }
           }
         }
@@ -495,6 +503,15 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
   const int64_t n_first = H.first + T.begin + tid;  // this lane's first bin
   const double t_first = ((double)n_first - H.t0_bin) * H.dt;
   const int n_steps = (T.n - tid + kBlock - 1) / kBlock;  // bins of this lane (may be 0)
+  // FP32 storage holds integer counts only (the host checks), FP64 any value
+  constexpr bool kIntData = sizeof(CT) == 4;
+  // counts are read one step ahead of their use so the load latency overlaps
+  // the theory evaluation of the current bin
+  const int64_t idx0 = H.off + T.begin + tid;
+  double d_next = 0.0;
+  if constexpr (MODE != kModeModel) {
+    if (n_steps > 0) d_next = load_count<CT>(J.counts, idx0);
+  }
   const int every = a.anchor_every;
 
   for (int k0 = 0; k0 < n_steps; k0 += every) {
@@ -512,7 +529,13 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
     const int k1 = min(n_steps, k0 + every);
   for (int k = k0; k < k1; ++k) {
     const double t = fma((double)k, h, t_first);
-    const int64_t idx = H.off + T.begin + tid + (int64_t)k * kBlock;
+    const int64_t idx = idx0 + (int64_t)k * kBlock;
+    double d_cur = 0.0;
+    if constexpr (MODE != kModeModel) {
+      d_cur = d_next;
+      const int kn = min(k + 1, n_steps - 1);
+      d_next = load_count<CT>(J.counts, idx0 + (int64_t)kn * kBlock);
+    }
 
     if constexpr (MODE != kModeGrad) {
       double A = 0.0;
@@ -533,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
         J.model_out[idx] = N;
       } else {
         double dN;
-        lane_cost += cost_term<COST, false>(load_count<CT>(J.counts, idx), N, dN);
+        lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
       }
     } else {
       double val[kSlots], d0[kSlots], d1[kSlots];
@@ -559,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
       }
       const double N = fma(n0 * E, 1.0 + A, nbkg);
       double dN;
-      lane_cost += cost_term<COST, true>(load_count<CT>(J.counts, idx), N, dN);
+      lane_cost += cost_term<COST, true, kIntData>(d_cur, N, dN);
       const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
       const double rNE = rE * n0;  // r N0 e^(-t/tau)
       g[0] = fma(rE, 1.0 + A, g[0]);
@@ -690,7 +713,7 @@ hipError_t launch_typed(const LaunchArgs &a, int count_f64, int shape, hipStream
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s) {
   if (a.n_blocks <= 0) return hipSuccess;
-  if (a.anchor_every < 1) return hipErrorInvalidValue;
+  if (a.anchor_every < 1 || a.anchor_every > 256) return hipErrorInvalidValue;
   if (mode == kModeModel) return launch_typed<MU_COST_CHI2, kModeModel>(a, count_f64, shape, s);
   if (a.cost_kind == MU_COST_CHI2)
     return mode == kModeGrad ? launch_typed<MU_COST_CHI2, kModeGrad>(a, count_f64, shape, s)

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -12,7 +13,7 @@ struct mu_ctx;
 
 namespace mu {
 
-constexpr int kDefaultTile = 4096;
+constexpr int kMinTile = 1024, kMaxTile = 65536;
 constexpr int kDefaultAnchor = 64;
 
 // Grow-only device buffer owned by a context.
@@ -34,9 +35,14 @@ struct HostBuf {
 void set_err(mu_ctx *ctx, const char *fmt, ...);
 mu_status hip_fail(mu_ctx *ctx, hipError_t e, const char *what);
 mu_status check_pair(mu_ctx *ctx, const mu_data *d, const mu_theory *th);
-mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,
-                    int cost_kind, int32_t ld, const double *params, unsigned mem, double *cost, double *grad,
-                    int64_t n_blocks);
+// n_vec vectors over one dataset in one launch (mode: cost, grad or model).
+mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *params,
+                       int32_t n_vec, unsigned mem, double *cost, double *histo, double *grad, double *model,
+                       int mode);
+struct TileSet;
+mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
+                    const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
+                    double *cost, double *grad, int64_t n_blocks, int anchor);
 
 }  // namespace mu
 
@@ -47,8 +53,14 @@ struct mu_ctx {
   bool own_stream = false;
   std::string err;
   int children = 0;
-  int tile_bins = mu::kDefaultTile;
+  int tile_bins = 0;  // 0: chosen per launch (tuned table, else heuristic)
   int anchor_every = mu::kDefaultAnchor;
+  // measured best (tile, anchor) per (shape, mode, cost, log2 of bin-evaluations)
+  struct Tuned {
+    int key, tile, anchor;
+  };
+  std::vector<Tuned> tuned;
+  int pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const;
   int specialize = 1;  // use the compiled shape kernels when a theory matches one
   hipEvent_t staging_free = nullptr;  // recorded after each upload from `staging`
   mu::DevBuf partial, dparams, dout, djobs;
@@ -64,6 +76,16 @@ struct mu_ctx {
   }
 };
 
+namespace mu {
+// Histogram and tile tables of one dataset for one tile size.
+struct TileSet {
+  int tile_bins = 0;
+  mu::DevHisto *d_histos = nullptr;  // with tile0 for this tile size
+  mu::DevTile *d_tiles = nullptr;
+  int32_t n_tiles = 0;
+};
+}  // namespace mu
+
 struct mu_data {
   mu_ctx *ctx = nullptr;
   void *counts = nullptr;  // FP32 or FP64 fit-range counts, concatenated
@@ -71,12 +93,12 @@ struct mu_data {
   int n_histo = 0;
   int max_row = 0;
   int64_t total = 0;
+  int64_t longest = 0;     // bins of the longest fit range
   std::vector<mu::DevHisto> hh;
-  mu::DevHisto *d_histos = nullptr;
-  mu::DevTile *d_tiles = nullptr;
-  int32_t n_tiles = 0;
-  int tiles_for = -1;  // tile size the tables were built for
-  mu_status build_tiles(int tile_bins);
+  std::deque<mu::TileSet> sets;  // one per tile size used so far (few); stable addresses
+  // Tables for `tile_bins`, built on first use and kept until destruction.
+  mu_status tiles(int tile_bins, const mu::TileSet **out);
+  void free_dev();
 };
 
 struct mu_theory {

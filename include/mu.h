@@ -277,6 +277,78 @@ mu_status mu_fit_batch(mu_ctx *ctx, int32_t n_fits, const mu_data *const *data, 
                        mu_cost cost_kind, int32_t ld, const double *start, const mu_fit_opts *opts,
                        double *params_out, double *cov_out, mu_fit_result *res);
 
+/* ------------------------------------------------------------------ seeder */
+
+/* A learned seeder proposes start parameters for fits of the exp*cos family
+ * (A(t) = A e^(-lambda t) cos(2 pi nu t + phi)) on histograms of 8192 bins of
+ * 0.001 us from t = 0.  It is a 1024-512-256-128-8 perceptron with ReLU, run
+ * with BF16 operands on the matrix cores and FP32 sums.  Input: the histogram
+ * rebinned by 8 to 1024 bins c_b, as the asymmetry (c_b - 8 Nbkg) /
+ * (8 N0 ebar_b) - 1 clipped to [-4, 4], where ebar_b is the lifetime decay
+ * averaged over bin b and N0, Nbkg solve m = N0 e + Nbkg for the means m of
+ * the first and last 256 bins (e: the decay averaged over each window).
+ * Outputs 0..4: A / 0.3,
+ * ln(lambda / 0.05) / ln 100, ln(nu / 0.1) / ln 500, cos phi, sin phi (outputs
+ * 5..7 carry no loss).  The start's N0 and Nbkg are those window estimates
+ * (the same rule as the default start).
+ *
+ * Parameter layout (FP32, mu_seeder_param_count() values): for each layer
+ * l = 0..3 its weights [out][in] row-major, then its biases [out].
+ *
+ * Training data come from the method itself (mu_gen_histos): parameters
+ * drawn from Philox4x32-10 with key `seed` and counters (sample, 0xFFFFFFFF,
+ * 0 / 1): N0 log-uniform in [1e2, 1e5], Nbkg uniform in [1, 10], A uniform in
+ * [0.05, 0.3], lambda log-uniform in [0.05, 5] /us, nu log-uniform in
+ * [0.1, 50] MHz, phi uniform in [0, 2 pi); expected counts of the 1024
+ * rebinned bins from Eq. 1; one Poisson draw per rebinned bin. */
+typedef struct {
+  uint64_t seed;          /* generator key */
+  uint64_t first_sample;  /* index of the first training sample */
+  int32_t batch;          /* samples per step */
+  int32_t steps;          /* optimiser steps; step k uses samples first + k batch .. */
+  float lr;               /* Adam learning rate at step 0 */
+  float lr_final_frac;    /* cosine decay to lr * lr_final_frac at the last step */
+} mu_seed_train_opts;
+
+int64_t mu_seeder_param_count(void);
+/* A seeder with the given initial parameters (host, FP32, finite). */
+mu_status mu_seeder_create(mu_ctx *ctx, const float *init_params, mu_seeder **out);
+mu_status mu_seeder_destroy(mu_seeder *s);
+mu_status mu_seeder_get_params(const mu_seeder *s, float *out);  /* host, param_count values */
+mu_status mu_seeder_get_grads(const mu_seeder *s, float *out);   /* gradient of the last step */
+int64_t mu_seeder_steps(const mu_seeder *s);                     /* Adam steps taken */
+
+/* Generate samples first .. first + n - 1 of the stream with key `seed`:
+ * theta [n][6] = (N0, Nbkg, A, lambda, nu, phi); with fine == 0 the 1024
+ * rebinned bins (expected count = sum of 8 fine bins, one Poisson draw each),
+ * with fine != 0 the 8192 bins of 0.001 us (one Poisson draw per bin):
+ * counts (FP32 integers) and mu (expected counts) of [n][1024] or [n][8192].
+ * Any output may be NULL (not all).  Poisson draws: inversion below a mean of
+ * 10, transformed rejection (Hoermann 1993) above; uniforms from Philox with
+ * counters (sample, bin or 0x10000 + fine bin, iteration). */
+mu_status mu_gen_histos(mu_ctx *ctx, uint64_t seed, uint64_t first, int32_t n, int32_t fine, unsigned mem,
+                        float *counts, double *theta, double *mu);
+
+/* Network output y [B][8] for BF16 inputs x [B][1024] (bit patterns). */
+mu_status mu_seeder_forward(mu_ctx *ctx, mu_seeder *s, const uint16_t *x_bf16, int32_t B, unsigned mem, float *y);
+/* One step on given inputs and targets [B][8]: loss (sum over the batch of
+ * sum_o w_o (y - t)^2, divided by B; w = 1 for outputs 0..4), gradient, and an
+ * Adam update (b1 0.9, b2 0.999, eps 1e-8) when update != 0.  loss may be NULL. */
+mu_status mu_seeder_train_step(mu_ctx *ctx, mu_seeder *s, const uint16_t *x_bf16, const float *targets, int32_t B,
+                               float lr, int32_t update, unsigned mem, float *loss);
+/* Train on freshly generated samples; loss_curve [steps] (host) may be NULL. */
+mu_status mu_seeder_train(mu_ctx *ctx, mu_seeder *s, const mu_seed_train_opts *opts, float *loss_curve);
+/* Start vectors (N0, Nbkg, A, lambda, nu, phi) for n datasets, each one
+ * histogram of 8192 integer counts in 0.001 us bins from t = 0 (else
+ * MU_E_ARG).  ok_out[i] = 0 when the decoded values are not finite or leave
+ * A in [0.01, 1], lambda in [0.005, 50], nu in [0.02, 250]; that row then
+ * holds the default start (A 0.175, lambda 0.5, nu sqrt 5, phi 0). */
+mu_status mu_seed_infer(mu_ctx *ctx, const mu_seeder *s, int32_t n, const mu_data *const *data, double *start_out,
+                        uint8_t *ok_out);
+/* Checkpoint (parameters, Adam moments, step count) and restore. */
+mu_status mu_seeder_save(const mu_seeder *s, const char *path);
+mu_status mu_seeder_load(mu_ctx *ctx, const char *path, mu_seeder **out);
+
 #ifdef __cplusplus
 }
 #endif

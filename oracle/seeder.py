@@ -2,8 +2,9 @@
 target encoding and the default start (test infrastructure only).
 
 The network maps a histogram of the exp*cos family, rebinned to 1024 bins and
-divided by its mean, to the hard-to-guess start parameters (A, lambda, nu,
-phi); N0 and Nbkg come from the first and last bins.  It is a 1024-512-256-
+turned into its asymmetry (counts less background over the lifetime decay,
+minus one; network_input), to the hard-to-guess start parameters (A, lambda,
+nu, phi); N0 and Nbkg come from the first and last bins.  It is a 1024-512-256-
 128-8 multilayer perceptron with ReLU; GEMM operands are BF16 and sums are
 kept wider.  Rounding points, in order (the GPU follows the same ones):
 
@@ -146,22 +147,45 @@ def encode(theta):
 
 
 TAU_MU = 2.1969811
+WIN = 32  # rebinned bins in each estimation window (256 bins of 0.001 us)
 
 
-def default_start(counts_fine, tau=TAU_MU):
-    """The non-learned start: N0 and Nbkg from the means of the first and last
-    256 bins of the 8192-bin histogram (two equations in two unknowns with the
-    lifetime decay averaged over each window), A = 0.175, lambda = 0.5 /us,
-    nu = sqrt(5) MHz, phi = 0."""
-    d = np.asarray(counts_fine, dtype=np.float64)
-    w = 256
-    t = np.arange(N_FINE) * DT_FINE
-    e = np.exp(-t / tau)
-    m1, m2 = d[:w].mean(), d[-w:].mean()
-    e1, e2 = e[:w].mean(), e[-w:].mean()
+def window_estimates(counts_coarse, tau=TAU_MU):
+    """N0 and Nbkg (per 0.001 us bin) from the means of the first and last 256
+    fine bins: two equations m = N0 e + Nbkg with e the lifetime decay averaged
+    over each window (geometric sums)."""
+    c = np.asarray(counts_coarse, dtype=np.float64)
+    m1 = c[:WIN].sum() / (WIN * REBIN)
+    m2 = c[-WIN:].sum() / (WIN * REBIN)
+    r = math.exp(-DT_FINE / tau)
+    w = WIN * REBIN
+    e1 = (1.0 - r ** w) / (w * (1.0 - r))
+    e2 = e1 * r ** (N_FINE - w)
     n0 = (m1 - m2) / (e1 - e2)
     nb = max(m2 - n0 * e2, 0.1)
     n0 = max(n0, 1.0)
+    return n0, nb
+
+
+def network_input(counts_coarse, tau=TAU_MU):
+    """The network's view of a rebinned histogram: the asymmetry
+    (c_b - 8 Nbkg) / (8 N0 ebar_b) - 1, with ebar_b the lifetime decay averaged
+    over rebinned bin b and N0, Nbkg from window_estimates; clipped to [-4, 4]."""
+    c = np.asarray(counts_coarse, dtype=np.float64)
+    n0, nb = window_estimates(c, tau)
+    r = math.exp(-DT_FINE / tau)
+    b = np.arange(N_COARSE, dtype=np.float64)
+    ebar = np.exp(-(REBIN * DT_FINE / tau) * b) * ((1.0 - r ** REBIN) / (REBIN * (1.0 - r)))
+    x = (c - REBIN * nb) / (REBIN * n0 * ebar) - 1.0
+    return np.clip(x, -4.0, 4.0)
+
+
+def default_start(counts_fine, tau=TAU_MU):
+    """The non-learned start: N0 and Nbkg from window_estimates, A = 0.175,
+    lambda = 0.5 /us, nu = sqrt(5) MHz (geometric midpoints of the ranges),
+    phi = 0."""
+    coarse = np.asarray(counts_fine, dtype=np.float64).reshape(N_COARSE, REBIN).sum(axis=1)
+    n0, nb = window_estimates(coarse, tau)
     return np.array([n0, nb, 0.175, 0.5, math.sqrt(5.0), 0.0])
 
 
@@ -218,8 +242,3 @@ def expected_coarse(theta_row, theory):
     return fine.reshape(N_COARSE, REBIN).sum(axis=1)
 
 
-def normalise(counts_coarse):
-    """Network input: rebinned counts divided by their mean (mean > 0)."""
-    c = np.asarray(counts_coarse, dtype=np.float64)
-    m = c.mean(axis=-1, keepdims=True)
-    return c / m, m

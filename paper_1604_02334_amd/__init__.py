@@ -22,3 +22,4 @@ from .api import (  # noqa: F401
     theory_check,
 )
 from .autograd import Chi2  # noqa: F401
+from .seeder import Seeder, gen_histos  # noqa: F401

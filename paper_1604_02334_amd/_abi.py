@@ -134,4 +134,8 @@ def exported_symbols():
                    "mu_ctx_set_specialize", "mu_autotune", "mu_histo_check", "mu_data_create",
                    "mu_data_destroy", "mu_data_bins", "mu_data_histos", "mu_data_is_f64", "mu_theory_check",
                    "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_chi2_eval", "mu_chi2_grad",
-                   "mu_chi2_batch", "mu_model_eval", "mu_fit_batch"])
+                   "mu_chi2_batch", "mu_model_eval", "mu_fit_batch",
+                   "mu_seeder_param_count", "mu_seeder_create", "mu_seeder_destroy", "mu_seeder_get_params",
+                   "mu_seeder_get_grads", "mu_seeder_steps", "mu_gen_histos", "mu_seeder_forward",
+                   "mu_seeder_train_step", "mu_seeder_train", "mu_seed_infer", "mu_seeder_save",
+                   "mu_seeder_load"])

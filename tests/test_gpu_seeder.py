@@ -1,0 +1,257 @@
+"""GPU seeder against the seeder oracle: generator parameters and expected
+counts (1e-12), Poisson statistics, network forward / backward / Adam parity
+(the GPU accumulates in FP32, the oracle in FP64: bar 1e-3 of the layer's
+scale), training, checkpoints, inference decode and fallback, and the gain of
+seeded over default starts on freshly generated fits."""
+
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import model
+from oracle import seeder as osd
+from paper_1604_02334_amd import api
+from paper_1604_02334_amd.seeder import Seeder, gen_histos, param_count
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _flat(Ws, bs):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in zip(Ws, bs)]).astype(np.float32)
+
+
+def _unflat(p):
+    Ws, bs, o = [], [], 0
+    for l in range(4):
+        k, n = osd.DIMS[l], osd.DIMS[l + 1]
+        Ws.append(p[o:o + n * k].reshape(n, k))
+        o += n * k
+        bs.append(p[o:o + n])
+        o += n
+    return Ws, bs
+
+
+def test_param_count():
+    assert param_count() == sum(osd.DIMS[l] * osd.DIMS[l + 1] + osd.DIMS[l + 1] for l in range(4))
+
+
+def test_generator_parameters_and_expected_counts(ctx):
+    _say("generator expected counts")
+    th_d = synth.theory_exp_cos()
+    for fine in (False, True):
+        counts, theta, mu = gen_histos(ctx, seed=77, first=1000, n=12, fine=fine, want_mu=True)
+        ref_th = osd.draw_theta(77, np.arange(1000, 1012))
+        np.testing.assert_allclose(theta, ref_th, rtol=1e-14)
+        for i in range(12):
+            if fine:
+                h = {"n_bins": 8192, "dt": 0.001, "t0_bin": 0.0, "first": 0, "last": 8191, "map_row": 0}
+                ref = model.model(th_d, h, theta[i])
+            else:
+                ref = osd.expected_coarse(theta[i], th_d)
+            np.testing.assert_allclose(mu[i], ref, rtol=1e-12)
+        assert np.all(counts == np.floor(counts)) and np.all(counts >= 0)
+
+
+def test_generator_poisson_statistics_and_reproducibility(ctx):
+    _say("generator statistics")
+    counts, theta, mu = gen_histos(ctx, seed=5, first=0, n=384, want_mu=True)
+    k = counts.astype(np.float64).ravel()
+    m = mu.ravel()
+    for lo, hi in ((0.0, 10.0), (10.0, 1e3), (1e3, 1e9)):
+        sel = (m >= lo) & (m < hi)
+        n = int(sel.sum())
+        if n < 500:
+            continue
+        z = (k[sel] - m[sel]) / np.sqrt(m[sel])
+        assert abs(z.mean()) < 5.0 / math.sqrt(n), (lo, z.mean())
+        assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / n) + 0.02, (lo, z.var())
+    # small means: empirical frequencies of k against the Poisson law (chi^2)
+    sel = (m > 2.0) & (m < 3.0)
+    if sel.sum() > 2000:
+        mm = m[sel]
+        kk = k[sel]
+        chi2 = 0.0
+        for v in range(0, 9):
+            expect = np.sum(np.exp(-mm) * mm ** v / math.factorial(v))
+            chi2 += (np.sum(kk == v) - expect) ** 2 / expect
+        assert chi2 < 40.0  # 9 cells, p ~ 5e-6
+    again, _, _ = gen_histos(ctx, seed=5, first=0, n=384)
+    np.testing.assert_array_equal(again, counts)
+    part, _, _ = gen_histos(ctx, seed=5, first=100, n=3)
+    np.testing.assert_array_equal(part, counts[100:103])
+    other, _, _ = gen_histos(ctx, seed=6, first=0, n=4)
+    assert not np.array_equal(other, counts[:4])
+
+
+def _random_inputs(B, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 3.0, (B, 1024))
+    return osd.bf16_bits(x), osd.from_bf16_bits(osd.bf16_bits(x))
+
+
+def _rows_agree(got, ref, tight=1e-4, loose=1e-2, frac=0.1):
+    """Rows agree to `tight` of the output scale, except rows where a hidden
+    value sat on a BF16 rounding boundary: there the FP32 sum of the GPU and
+    the FP64 sum of the oracle may round to neighbouring BF16 values and the
+    flip propagates (bounded by `loose`; at most `frac` of the rows)."""
+    scale = np.max(np.abs(ref)) + 1e-30
+    err = np.max(np.abs(got - ref), axis=1) / scale
+    return np.mean(err > tight) <= frac and np.max(err) <= loose, (np.mean(err > tight), np.max(err))
+
+
+def test_forward_parity(ctx):
+    _say("seeder forward")
+    Ws, bs = osd.init_params(11)
+    bs = [b + np.float32(0.01) * np.arange(b.size, dtype=np.float32) for b in bs]
+    S = Seeder(ctx, _flat(Ws, bs))
+    for B in (96, 1, 130):
+        xb, xf = _random_inputs(B, B)
+        y = S.forward(xb)
+        ref, _ = osd.forward(Ws, bs, xf)
+        ok, stats = _rows_agree(y, ref)
+        assert ok, (B, stats)
+
+
+def test_backward_and_adam_parity(ctx):
+    _say("seeder backward / adam")
+    Ws, bs = osd.init_params(12)
+    S = Seeder(ctx, _flat(Ws, bs))
+    B = 200
+    xb, xf = _random_inputs(B, 3)
+    T = osd.encode(osd.draw_theta(3, np.arange(B))).astype(np.float32)
+    loss = S.train_step(xb, T, lr=1e-3, update=False)
+    Y, cache = osd.forward(Ws, bs, xf)
+    ref_loss, dY = osd.loss_and_grad(Y, T)
+    assert loss == pytest.approx(ref_loss, rel=1e-4)
+    dWs, dbs = osd.backward(cache, dY)
+    gW, gb = _unflat(S.grads())
+    for l in range(4):
+        for got, ref in ((gW[l], dWs[l]), (gb[l], dbs[l])):
+            # batch sums average out the rare BF16 rounding flips of the forward pass
+            scale = np.max(np.abs(ref)) + 1e-30
+            assert np.max(np.abs(got - ref)) <= 1e-2 * scale, (l, np.max(np.abs(got - ref)) / scale)
+            assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref), l
+    # one Adam step from the same start
+    S2 = Seeder(ctx, _flat(Ws, bs))
+    S2.train_step(xb, T, lr=1e-3, update=True)
+    assert S2.steps == 1
+    got = S2.params()
+    params = [np.asarray(p, dtype=np.float64) for p in sum(([W.ravel(), b] for W, b in zip(Ws, bs)), [])]
+    grads = sum(([dW.ravel(), db] for dW, db in zip(dWs, dbs)), [])
+    zeros = [np.zeros_like(p) for p in params]
+    new = np.concatenate(osd.adam(params, grads, zeros, [np.zeros_like(p) for p in params], 1, 1e-3))
+    diff = np.abs(got - new)
+    # a gradient component near zero may take either sign: allow a tiny fraction
+    assert np.mean(diff > 1e-4) < 1e-3, np.mean(diff > 1e-4)
+
+
+def test_training_reduces_loss_and_checkpoint(ctx):
+    _say("seeder training / checkpoint")
+    Ws, bs = osd.init_params(13)
+    S = Seeder(ctx, _flat(Ws, bs))
+    curve = S.train(seed=21, steps=300, batch=256, lr=1e-3)
+    assert np.all(np.isfinite(curve))
+    assert curve[-20:].mean() < 0.6 * curve[:20].mean(), (curve[:20].mean(), curve[-20:].mean())
+    xb, _ = _random_inputs(8, 4)
+    y = S.forward(xb)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "seeder.bin")
+        S.save(path)
+        S2 = Seeder.load(ctx, path)
+        np.testing.assert_array_equal(S2.params(), S.params())
+        assert S2.steps == S.steps == 300
+        np.testing.assert_array_equal(S2.forward(xb), y)
+
+
+def _fine_datas(ctx, seed, first, n):
+    counts, theta, _ = gen_histos(ctx, seed=seed, first=first, n=n, fine=True)
+    h = [{"n_bins": 8192, "dt": 0.001, "t0_bin": 0.0, "first": 0, "last": 8191, "map_row": 0}]
+    datas = [api.Data(ctx, h, [counts[i].astype(np.float64)]) for i in range(n)]
+    return counts, theta, datas, h
+
+
+def test_inference_decode_and_fallback(ctx):
+    _say("seeder inference")
+    Ws, bs = osd.init_params(14)
+    S = Seeder(ctx, _flat(Ws, bs))
+    S.train(seed=31, steps=60, batch=256, lr=1e-3)
+    Ws2, bs2 = _unflat(S.params())
+    counts, theta, datas, h = _fine_datas(ctx, 99, 0, 24)
+    start, ok = S.infer(datas)
+    for i in range(24):
+        coarse = counts[i].astype(np.float64).reshape(1024, 8).sum(axis=1)
+        x = osd.network_input(coarse)
+        Y, _ = osd.forward(Ws2, bs2, x[None])
+        ref, ref_ok = osd.decode(Y[0], counts[i])
+        np.testing.assert_allclose(start[i, :2], ref[:2], rtol=1e-9)
+        if ref_ok and ok[i]:
+            np.testing.assert_allclose(start[i, 2:5], ref[2:5], rtol=2e-2)
+            assert math.cos(start[i, 5] - ref[5]) > 0.999
+    # a network whose nu output leaves the valid range falls back to the default start
+    bs_bad = [b.copy() for b in bs]
+    bs_bad[3][2] = 10.0
+    B = Seeder(ctx, _flat(Ws, bs_bad))
+    start, ok = B.infer(datas[:4])
+    assert not ok.any()
+    for i in range(4):
+        np.testing.assert_allclose(start[i], osd.default_start(counts[i]), rtol=1e-9)
+
+
+def _wrap_phase(p):
+    q = p.copy()
+    q[5] = (q[5] + math.pi) % (2 * math.pi) - math.pi
+    return q
+
+
+def test_seeded_fits_beat_default_starts(ctx):
+    """Reduced C5: train on 256k generated histograms, then fit fresh ones from
+    the seeder's starts and from the default start; a fit succeeds when it
+    reaches the fit started at the truth (within 1e-6 of max(|p|, sigma))."""
+    _say("seeded vs default fits")
+    Ws, bs = osd.init_params(15)
+    S = Seeder(ctx, _flat(Ws, bs))
+    S.train(seed=41, steps=500, batch=512, lr=2e-3)
+    n = 96
+    counts, theta, datas, h = _fine_datas(ctx, 4242, 10_000_000, n)
+    th = api.Theory(ctx, synth.theory_exp_cos())
+    ths = [th] * n
+    seeded, ok = S.infer(datas)
+    default = np.stack([osd.default_start(counts[i]) for i in range(n)])
+    p_ref, cov, r_ref = api.fit_batch(ctx, datas, ths, theta)
+    p_s, _, r_s = api.fit_batch(ctx, datas, ths, seeded, want_cov=False)
+    p_d, _, r_d = api.fit_batch(ctx, datas, ths, default, want_cov=False)
+
+    def success(p):
+        good = 0
+        for i in range(n):
+            sig = np.sqrt(np.abs(np.diag(cov[i])))
+            a, b = _wrap_phase(p[i]), _wrap_phase(p_ref[i])
+            # A < 0 with phi + pi is the same curve
+            if a[2] < 0:
+                a[2] = -a[2]
+                a[5] = (a[5] + 2 * math.pi) % (2 * math.pi) - math.pi
+            d = np.abs(a - b)
+            d[5] = min(d[5], 2 * math.pi - d[5])
+            good += bool(np.all(d <= 1e-6 * np.maximum(np.abs(b), sig)))
+        return good
+
+    s_seed, s_def = success(p_s), success(p_d)
+    print(f"[result] ok {ok.mean():.3f} seeded {s_seed}/{n} default {s_def}/{n} "
+          f"fcn seeded {np.mean([r['n_fcn'] for r in r_s]):.1f} default {np.mean([r['n_fcn'] for r in r_d]):.1f}",
+          flush=True)
+    assert s_seed > s_def

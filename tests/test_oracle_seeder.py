@@ -104,3 +104,23 @@ def test_encode_decode_round_trip():
     bad = T[0].copy()
     bad[2] = 9.0  # nu far outside the trained range
     assert not seeder.decode(bad, d)[1]
+
+
+def test_network_input_of_noiseless_histogram_is_the_asymmetry():
+    """Noiseless data: zero for A = 0; otherwise the rebin-averaged A(t) up to
+    the offset and scale that the window estimates of N0 and Nbkg introduce."""
+    th = synth.theory_exp_cos()
+    for A in (0.0, 0.2):
+        row = np.array([20000.0, 3.0, A, 0.3, 0.7, 0.4])
+        mu = seeder.expected_coarse(row, th)
+        x = seeder.network_input(mu)
+        t = (np.arange(seeder.N_FINE) * seeder.DT_FINE).reshape(seeder.N_COARSE, seeder.REBIN)
+        e = np.exp(-t / seeder.TAU_MU)
+        asym = (e * A * np.exp(-0.3 * t) * np.cos(2 * np.pi * 0.7 * t + 0.4)).sum(axis=1) / e.sum(axis=1)
+        if A == 0.0:
+            assert np.max(np.abs(x)) < 1e-9
+        else:
+            # the windows see part of the oscillation: equal up to offset and scale
+            assert np.corrcoef(x, asym)[0, 1] > 0.999
+    n0, nb = seeder.window_estimates(seeder.expected_coarse(np.array([5000.0, 7.0, 0.0, 0.3, 0.7, 0.4]), th))
+    assert n0 == pytest.approx(5000.0, rel=1e-9) and nb == pytest.approx(7.0, rel=1e-9)

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -34,10 +35,17 @@ if ROOT not in sys.path:
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 vector
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
-# Algorithmic FP64 flops per bin of the cost pass on this theory (FMA = 2):
-# lifetime step 1, damped rotation 6, Kubo-Toyabe step and polynomial 9,
-# asymmetry 3, histogram model 3, chi^2 term 4, accumulation 1.
-FLOPS_PER_BIN_CHI2 = 27
+# Algorithmic FP64 flops per bin of the cost pass on this theory with the
+# recurrence formulation (FMA = 2 flops): lifetime step 1, exponential step 1,
+# rotation 6, product 1, first term 2, Kubo-Toyabe (two Gaussian steps, time,
+# polynomial) 10, second term 2, histogram model 4, chi^2 term with the
+# refined reciprocal 8, accumulation 1.
+FLOPS_PER_BIN_CHI2 = 36
+# The same count with every FP64 instruction as one operation (FMA = 1), and
+# the FP64 vector issue rate it is set against: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 39.3 T lane-operations per second.
+OPS_PER_BIN_CHI2 = 26
+PEAK_FP64_TOPS = 39.3
 BYTES_PER_BIN = 4         # one FP32 count streamed per bin evaluation
 
 
@@ -87,12 +95,150 @@ def _cpu_baseline(cfg, counts, stencil, budget_s=12.0):
                       f"({bins} bin evaluations, {dt:.1f} s, numpy + math.fsum, one thread)"}
 
 
+def _wrap(p):
+    q = np.array(p, dtype=np.float64)
+    if q[2] < 0:  # A < 0 with phi + pi is the same curve
+        q[2] = -q[2]
+        q[5] += math.pi
+    q[5] = (q[5] + math.pi) % (2 * math.pi) - math.pi
+    return q
+
+
+def _same_minimum(p, ref, cov, tol=1e-6):
+    a, b = _wrap(p), _wrap(ref)
+    d = np.abs(a - b)
+    d[5] = min(d[5], 2 * math.pi - d[5])
+    sig = np.sqrt(np.abs(np.diag(cov)))
+    return bool(np.all(d <= tol * np.maximum(np.abs(b), sig)))
+
+
+def _fits_c4(api, ctx, n_sets=512, n_plain=32):
+    """512 independent uneven datasets (4 theory families), all fitted to
+    convergence by the batched path, and a subset by the plain path."""
+    import synth
+
+    cfg = synth.config_c4(n_sets=n_sets)
+    rng = cfg["rng"]
+    sets = cfg["sets"]
+    ths, datas = [], []
+    for s in sets:
+        th = api.Theory(ctx, s["theory"])
+        grid = api.Data(ctx, s["histos"], [np.zeros(s["histos"][0]["n_bins"])])
+        means = api.model_eval(ctx, grid, th, s["p_true"])
+        grid.close()
+        ths.append(th)
+        datas.append(api.Data(ctx, s["histos"], [synth.draw_counts(means, rng)]))
+    ld = 6
+    start = np.zeros((n_sets, ld))
+    for j, s in enumerate(sets):
+        start[j, :s["start"].size] = s["start"]
+    bins = sum(d.n_bins for d in datas)
+    t0 = time.perf_counter()
+    pb, covb, rb = api.fit_batch(ctx, datas, ths, start)
+    tb = time.perf_counter() - t0
+    sub = list(range(n_plain))
+    t0 = time.perf_counter()
+    pb2, _, rb2 = api.fit_batch(ctx, [datas[j] for j in sub], [ths[j] for j in sub], start[sub], want_cov=False)
+    tb2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pp, _, rp = api.fit_batch(ctx, [datas[j] for j in sub], [ths[j] for j in sub], start[sub],
+                              analytic_grad=False, batched=False, want_cov=False)
+    tp = time.perf_counter() - t0
+    agree = 0
+    for k, j in enumerate(sub):
+        n = sets[j]["start"].size
+        sig = np.sqrt(np.abs(np.diag(covb[j])))[:n]
+        agree += bool(np.all(np.abs(pp[k, :n] - pb[j, :n]) <= 1e-5 * np.maximum(np.abs(pb[j, :n]), sig)))
+    for d in datas:
+        d.close()
+    return {"datasets": n_sets, "bins": int(bins),
+            "batched": {"fits": n_sets, "seconds": round(tb, 3), "fits_per_s": round(n_sets / tb, 2),
+                        "converged": int(sum(r["status"] == 0 for r in rb)),
+                        "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in rb])), 1)},
+            "batched_subset": {"fits": n_plain, "seconds": round(tb2, 3), "fits_per_s": round(n_plain / tb2, 2)},
+            "plain_subset": {"fits": n_plain, "seconds": round(tp, 3), "fits_per_s": round(n_plain / tp, 2),
+                             "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in rp])), 1),
+                             "same_minimum_as_batched": agree},
+            "speedup_batched_vs_plain_subset": round(tp / tb2, 1)}
+
+
+def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_plain=100):
+    """Learned seeder: training on method-generated histograms, then fits of
+    fresh histograms from seeded, default and true starts."""
+    import synth
+    from paper_1604_02334_amd.seeder import Seeder, gen_histos, param_count
+
+    rng = np.random.default_rng(5)
+    # He-uniform start (last layer x0.1), zero biases, from a fixed seed
+    dims = (1024, 512, 256, 128, 8)
+    init = []
+    for l in range(4):
+        b = math.sqrt(6.0 / dims[l]) * (0.1 if l == 3 else 1.0)
+        init += [rng.uniform(-b, b, dims[l] * dims[l + 1]), np.zeros(dims[l + 1])]
+    init = np.concatenate(init).astype(np.float32)
+    assert init.size == param_count()
+    S = Seeder(ctx, init)
+    steps = train_samples // batch
+    t0 = time.perf_counter()
+    curve = S.train(seed=160402334, steps=steps, batch=batch, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    counts, theta, _ = gen_histos(ctx, seed=1604, first=0, n=n_eval, fine=True)
+    h = [{"n_bins": 8192, "dt": 0.001, "t0_bin": 0.0, "first": 0, "last": 8191, "map_row": 0}]
+    datas = [api.Data(ctx, h, [counts[i].astype(np.float64)]) for i in range(n_eval)]
+    th = api.Theory(ctx, synth.theory_exp_cos())
+    ths = [th] * n_eval
+    t0 = time.perf_counter()
+    seeded, ok = S.infer(datas)
+    t_inf = time.perf_counter() - t0
+    # default start: the same window estimates of N0 and Nbkg, fixed A, lambda, nu, phi
+    default = seeded.copy()
+    default[:, 2:] = [0.175, 0.5, math.sqrt(5.0), 0.0]
+    t0 = time.perf_counter()
+    p_ref, cov, r_ref = api.fit_batch(ctx, datas, ths, theta)
+    t_ref = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p_s, _, r_s = api.fit_batch(ctx, datas, ths, seeded, want_cov=False)
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p_d, _, r_d = api.fit_batch(ctx, datas, ths, default, want_cov=False)
+    t_d = time.perf_counter() - t0
+    sub = list(range(n_plain))
+    t0 = time.perf_counter()
+    p_p, _, r_p = api.fit_batch(ctx, [datas[i] for i in sub], [th] * n_plain, default[sub],
+                                analytic_grad=False, batched=False, want_cov=False)
+    t_p = time.perf_counter() - t0
+    ok_s = [_same_minimum(p_s[i], p_ref[i], cov[i]) for i in range(n_eval)]
+    ok_d = [_same_minimum(p_d[i], p_ref[i], cov[i]) for i in range(n_eval)]
+    ok_p = [_same_minimum(p_p[k], p_ref[i], cov[i]) for k, i in enumerate(sub)]
+    err_s = [np.max(np.abs(_wrap(seeded[i])[2:5] - _wrap(p_ref[i])[2:5]) / np.abs(_wrap(p_ref[i])[2:5]))
+             for i in range(n_eval)]
+    for d in datas:
+        d.close()
+    S.close()
+    return {"train": {"samples": steps * batch, "steps": steps, "seconds": round(t_train, 2),
+                      "samples_per_s": round(steps * batch / t_train), "loss_first": float(curve[:20].mean()),
+                      "loss_last": float(curve[-20:].mean())},
+            "eval_fits": n_eval, "infer_seconds": round(t_inf, 3), "seeder_ok": float(ok.mean()),
+            "median_seed_rel_error_A_lambda_nu": float(np.median(err_s)),
+            "seeded": {"success": float(np.mean(ok_s)), "fits_per_s": round(n_eval / (t_s + t_inf), 1),
+                       "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in r_s])), 1)},
+            "default": {"success": float(np.mean(ok_d)), "fits_per_s": round(n_eval / t_d, 1),
+                        "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in r_d])), 1)},
+            "truth_start_reference": {"fits_per_s": round(n_eval / t_ref, 1)},
+            "plain_default_subset": {"fits": n_plain, "success": float(np.mean(ok_p)),
+                                     "fits_per_s": round(n_plain / t_p, 2),
+                                     "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in r_p])), 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fits", action="store_true", help="skip the fit and seeder sections")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only the timed stencil launches (for hardware-counter runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -136,6 +282,13 @@ def main():
     # measured tile / anchor choice for both launches (untimed)
     tune_eval = api.autotune(ctx, data, th, s_dev)
     tune_grad = api.autotune(ctx, data, th, p_dev, grad=True)
+    if args.stencil_only:
+        for _ in range(args.steps):
+            api.chi2_eval(ctx, data, th, s_dev)
+        torch.cuda.synchronize()
+        print(json.dumps({"stencil_launches": args.steps, "tile": tune_eval[0], "anchor": tune_eval[1]}))
+        ctx.close()
+        return
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -185,10 +338,14 @@ def main():
                      "kernel": "eval_kernel<chi2, cost, float>", "kernel_ms": round(k_ms, 5),
                      "flops_per_bin": FLOPS_PER_BIN_CHI2, "bins_per_launch": k_bins},
         "extra": {"stencil_kernel_gbin_s": round(k_bins / (k_ms * 1e-3) / 1e9, 2),
+                  "fp64_op_issue_frac": round(OPS_PER_BIN_CHI2 * k_bins / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TOPS, 4),
                   "tuned_stencil": {"tile": tune_eval[0], "anchor": tune_eval[1]},
                   "tuned_grad": {"tile": tune_grad[0], "anchor": tune_grad[1]},
                   "single_eval_host_latency_us": round(lat_us, 2)},
     }
+    if not args.no_fits:
+        out["fits_c4"] = _fits_c4(api, ctx)
+        out["seeder_c5"] = _seeder_c5(api, ctx)
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(cfg, counts, stencil)
     print(json.dumps(out), flush=True)

@@ -391,7 +391,10 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
   }
   d->total = total;
   const size_t esz = d->f64 ? sizeof(double) : sizeof(float);
-  hipError_t e = hipMalloc(&d->counts, (size_t)total * esz);
+  // one lane step (256 values) of zero padding: kernels read each lane's next
+  // count one step ahead, and the read after a lane's last bin lands here
+  const size_t padded = ((size_t)total + kBlock) * esz;
+  hipError_t e = hipMalloc(&d->counts, padded);
   if (e != hipSuccess) {
     delete d;
     set_err(ctx, "device allocation for %lld bins failed", (long long)total);
@@ -399,7 +402,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
   }
   // pack on the host, upload once
   {
-    std::vector<char> buf((size_t)total * esz);
+    std::vector<char> buf(padded, 0);
     for (int j = 0; j < n_histo; ++j) {
       const DevHisto &x = d->hh[j];
       for (int64_t i = 0; i < x.n; ++i) {
@@ -1056,8 +1059,33 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   bool have_ref = false;
   int bt = 0, ba = 0;
   float best = 1e30f;
-  for (int tile = kMinTile; tile <= kMaxTile && st == MU_OK; tile *= 2) {
+  // candidates: powers of two, and tiles that split every histogram into m
+  // near-equal parts with the workgroup count just below a whole number of
+  // waves of resident workgroups (the last wave of a launch is otherwise
+  // partly idle)
+  std::vector<int> cand;
+  for (int tile = kMinTile; tile <= kMaxTile; tile *= 2) {
     if (tile / 2 >= d->longest && tile > kMinTile) break;
+    cand.push_back(tile);
+  }
+  {
+    const int shape = ctx->specialize ? th->shape : kShapeGeneric;
+    const int per_cu = eval_blocks_per_cu(mode, cost_kind, d->f64, shape);
+    const int64_t cap = (int64_t)std::max(per_cu, 1) * std::max(ctx->n_cu, 1);
+    for (int m = 1; m <= 64; ++m) {
+      int tile = (int)(((d->longest + m - 1) / m + kBlock - 1) / kBlock * kBlock);
+      if (tile < kMinTile || tile > kMaxTile) continue;
+      int64_t blocks = 0;
+      for (const DevHisto &x : d->hh) blocks += (x.n + tile - 1) / tile;
+      blocks *= n_vec;
+      const int64_t waves = (blocks + cap - 1) / cap;
+      if ((double)blocks / (double)(waves * cap) >= 0.9 &&
+          std::find(cand.begin(), cand.end(), tile) == cand.end())
+        cand.push_back(tile);
+    }
+  }
+  for (size_t ci = 0; ci < cand.size() && st == MU_OK; ++ci) {
+    const int tile = cand[ci];
     for (int anchor : {32, 64, 128, 256}) {
       ctx->tile_bins = tile;
       ctx->anchor_every = anchor;

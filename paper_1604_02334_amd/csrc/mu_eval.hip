@@ -164,6 +164,8 @@ __device__ double resolve_ref(const DevTheory *th, DevRef r, const double *p, in
 
 // ----------------------------------------------------- primitive recurrences
 
+__host__ __device__ constexpr int prim_nargs(int kind) { return (kind == MU_GE || kind == MU_TF) ? 2 : 1; }
+
 // Step constant w (0 or 1) of a primitive for the lane step h.
 __device__ __forceinline__ double step_const(int kind, int w, double a0, double a1, double h) {
   switch (kind) {
@@ -329,7 +331,48 @@ __device__ __forceinline__ DevJob job_of(const LaunchArgs &a, int b, int &job) {
   return a.jobs[job];
 }
 
-// ------------------------------------------------------------ merge (last WG)
+// ------------------------------------------------------------ merge kernel
+
+// Compensated sum of slot component `c` over tiles [k0, k1): eight independent
+// loads in flight, lanes of the eight-wide stripe combined in a fixed order.
+__device__ double sum_slots(const double *P, int k0, int k1, int c) {
+  Pair acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = Pair{0.0, 0.0};
+  int k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)(k + u) * kSlot + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = pair_add(acc[u], Pair{v[u], 0.0});
+  }
+  for (int u = 0; k < k1; ++k, ++u) acc[u] = pair_add(acc[u], Pair{P[(int64_t)k * kSlot + c], 0.0});
+  Pair t = acc[0];
+#pragma unroll
+  for (int u = 1; u < 8; ++u) t = pair_add(t, acc[u]);
+  return pair_value(t);
+}
+
+// Same for the cost pairs (s, c) of tiles [k0, k1).
+__device__ double sum_slot_pairs(const double *P, int k0, int k1) {
+  Pair acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = Pair{0.0, 0.0};
+  int k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    Pair v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = Pair{P[(int64_t)(k + u) * kSlot], P[(int64_t)(k + u) * kSlot + 1]};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = pair_add(acc[u], v[u]);
+  }
+  for (int u = 0; k < k1; ++k, ++u) acc[u] = pair_add(acc[u], Pair{P[(int64_t)k * kSlot], P[(int64_t)k * kSlot + 1]});
+  Pair t = acc[0];
+#pragma unroll
+  for (int u = 1; u < 8; ++u) t = pair_add(t, acc[u]);
+  return pair_value(t);
+}
 
 // Merge the tile slots of job J in a fixed order and write its outputs.
 template <int MODE>
@@ -355,9 +398,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
     for (int h = tid; h < J.n_histo; h += kBlock) {
       const int k0 = J.histos[h].tile0;
       const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
-      Pair q{0.0, 0.0};
-      for (int k = k0; k < k1; ++k) q = pair_add(q, Pair{P[k * kSlot], P[k * kSlot + 1]});
-      J.histo_out[h] = pair_value(q);
+      J.histo_out[h] = sum_slot_pairs(P, k0, k1);
     }
   }
 
@@ -390,9 +431,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
         if (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN) {
           const int k0 = J.histos[h].tile0;
           const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
-          Pair q{0.0, 0.0};
-          for (int k = k0; k < k1; ++k) q = pair_add(q, Pair{P[k * kSlot + 2 + r], 0.0});
-          s = pair_value(q);
+          s = sum_slots(P, k0, k1, 2 + r);
           const int m = th->map[J.histos[h].map_row * th->n_slots + ref.slot];
           pi = ref.kind == MU_REF_PAR ? m : -(2 + m);
         }
@@ -502,121 +541,126 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
 
   const int64_t n_first = H.first + T.begin + tid;  // this lane's first bin
   const double t_first = ((double)n_first - H.t0_bin) * H.dt;
-  const int n_steps = (T.n - tid + kBlock - 1) / kBlock;  // bins of this lane (may be 0)
+  // every lane has n_full bins; lanes below T.n % 256 have one more
+  const int n_full = T.n / kBlock;
+  const bool extra = tid < (T.n % kBlock);
+  const int n_max = n_full + ((T.n % kBlock) != 0 ? 1 : 0);  // uniform
   // FP32 storage holds integer counts only (the host checks), FP64 any value
   constexpr bool kIntData = sizeof(CT) == 4;
   // counts are read one step ahead of their use so the load latency overlaps
-  // the theory evaluation of the current bin
+  // the theory evaluation of the current bin; the read after a lane's last
+  // bin stays inside the counts buffer, which the host pads by one step
   const int64_t idx0 = H.off + T.begin + tid;
+  const CT *cp = static_cast<const CT *>(J.counts) + idx0;
   double d_next = 0.0;
-  if constexpr (MODE != kModeModel) {
-    if (n_steps > 0) d_next = load_count<CT>(J.counts, idx0);
-  }
+  if constexpr (MODE != kModeModel) d_next = (double)cp[0];
   const int every = a.anchor_every;
+  double t = t_first;
 
-  for (int k0 = 0; k0 < n_steps; k0 += every) {
-    // exact re-evaluation (anchor) at the first step of the segment
-    {
-      const double t = fma((double)k0, h, t_first);
-      E = x_exp(neg_inv_tau * t);
-#pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        const int kt = s / kMaxFT, f = s % kMaxFT;
-        if (kt < n_terms && f < Sh::nf(ts, kt))
-          anchor(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
-      }
-    }
-    const int k1 = min(n_steps, k0 + every);
-  for (int k = k0; k < k1; ++k) {
-    const double t = fma((double)k, h, t_first);
+  // one bin: value, cost term (or model value), gradient, then advance
+  auto bin_step = [&](int k) {
     const int64_t idx = idx0 + (int64_t)k * kBlock;
     double d_cur = 0.0;
     if constexpr (MODE != kModeModel) {
       d_cur = d_next;
-      const int kn = min(k + 1, n_steps - 1);
-      d_next = load_count<CT>(J.counts, idx0 + (int64_t)kn * kBlock);
+      d_next = (double)cp[(int64_t)(k + 1) * kBlock];
     }
-
-    if constexpr (MODE != kModeGrad) {
-      double A = 0.0;
+      if constexpr (MODE != kModeGrad) {
+        double A = 0.0;
 #pragma unroll
-      for (int kt = 0; kt < kMaxT; ++kt) {
-        if (kt < n_terms) {
-          double prod = 1.0;
+        for (int kt = 0; kt < kMaxT; ++kt) {
+          if (kt < n_terms) {
+            double prod = 1.0;
 #pragma unroll
-          for (int f = 0; f < kMaxFT; ++f) {
-            const int s = kt * kMaxFT + f;
-            if (f < Sh::nf(ts, kt)) prod *= value(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], s0[s]);
+            for (int f = 0; f < kMaxFT; ++f) {
+              const int s = kt * kMaxFT + f;
+              if (f < Sh::nf(ts, kt)) prod *= value(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], s0[s]);
+            }
+            A = fma(coef[kt] * R[2 + kt], prod, A);
           }
-          A = fma(coef[kt] * R[2 + kt], prod, A);
         }
-      }
-      const double N = fma(n0 * E, 1.0 + A, nbkg);
-      if constexpr (MODE == kModeModel) {
-        J.model_out[idx] = N;
+        const double N = fma(n0 * E, 1.0 + A, nbkg);
+        if constexpr (MODE == kModeModel) {
+          J.model_out[idx] = N;
+        } else {
+          double dN;
+          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
+        }
       } else {
+        double val[kSlots], d0[kSlots], d1[kSlots];
+        double tprod[kMaxT];
+        double A = 0.0;
+#pragma unroll
+        for (int kt = 0; kt < kMaxT; ++kt) {
+          tprod[kt] = 1.0;
+          if (kt < n_terms) {
+#pragma unroll
+            for (int f = 0; f < kMaxFT; ++f) {
+              const int s = kt * kMaxFT + f;
+              val[s] = 1.0;
+              d0[s] = d1[s] = 0.0;
+              if (f < Sh::nf(ts, kt)) {
+                val[s] = value_grad(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], s0[s], s1[s], d0[s],
+                                    d1[s]);
+                tprod[kt] *= val[s];
+              }
+            }
+            A = fma(coef[kt] * R[2 + kt], tprod[kt], A);
+          }
+        }
+        const double N = fma(n0 * E, 1.0 + A, nbkg);
         double dN;
-        lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
-      }
-    } else {
-      double val[kSlots], d0[kSlots], d1[kSlots];
-      double tprod[kMaxT];
-      double A = 0.0;
+        lane_cost += cost_term<COST, true, kIntData>(d_cur, N, dN);
+        const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
+        const double rNE = rE * n0;  // r N0 e^(-t/tau)
+        g[0] = fma(rE, 1.0 + A, g[0]);
+        g[1] += dN;
 #pragma unroll
-      for (int kt = 0; kt < kMaxT; ++kt) {
-        tprod[kt] = 1.0;
-        if (kt < n_terms) {
+        for (int kt = 0; kt < kMaxT; ++kt) {
+          if (kt < n_terms) {
+            const double ck = coef[kt];
+            g[2 + kt] = fma(rNE * ck, tprod[kt], g[2 + kt]);
+            const double ca = rNE * ck * R[2 + kt];
 #pragma unroll
-          for (int f = 0; f < kMaxFT; ++f) {
-            const int s = kt * kMaxFT + f;
-            val[s] = 1.0;
-            d0[s] = d1[s] = 0.0;
-            if (f < Sh::nf(ts, kt)) {
-              val[s] = value_grad(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], s0[s], s1[s], d0[s],
-                                  d1[s]);
-              tprod[kt] *= val[s];
-            }
-          }
-          A = fma(coef[kt] * R[2 + kt], tprod[kt], A);
-        }
-      }
-      const double N = fma(n0 * E, 1.0 + A, nbkg);
-      double dN;
-      lane_cost += cost_term<COST, true, kIntData>(d_cur, N, dN);
-      const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
-      const double rNE = rE * n0;  // r N0 e^(-t/tau)
-      g[0] = fma(rE, 1.0 + A, g[0]);
-      g[1] += dN;
+            for (int f = 0; f < kMaxFT; ++f) {
+              const int s = kt * kMaxFT + f;
+              if (f < Sh::nf(ts, kt)) {
+                double others = ca;
 #pragma unroll
-      for (int kt = 0; kt < kMaxT; ++kt) {
-        if (kt < n_terms) {
-          const double ck = coef[kt];
-          g[2 + kt] = fma(rNE * ck, tprod[kt], g[2 + kt]);
-          const double ca = rNE * ck * R[2 + kt];
-#pragma unroll
-          for (int f = 0; f < kMaxFT; ++f) {
-            const int s = kt * kMaxFT + f;
-            if (f < Sh::nf(ts, kt)) {
-              double others = ca;
-#pragma unroll
-              for (int f2 = 0; f2 < kMaxFT; ++f2)
-                if (f2 != f && f2 < Sh::nf(ts, kt)) others *= val[kt * kMaxFT + f2];
-              g[kArg0 + 2 * s] = fma(others, d0[s], g[kArg0 + 2 * s]);
-              g[kArg0 + 2 * s + 1] = fma(others, d1[s], g[kArg0 + 2 * s + 1]);
+                for (int f2 = 0; f2 < kMaxFT; ++f2)
+                  if (f2 != f && f2 < Sh::nf(ts, kt)) others *= val[kt * kMaxFT + f2];
+                g[kArg0 + 2 * s] = fma(others, d0[s], g[kArg0 + 2 * s]);
+                g[kArg0 + 2 * s + 1] = fma(others, d1[s], g[kArg0 + 2 * s + 1]);
+              }
             }
           }
         }
       }
-    }
 
-    // advance every state by one lane step
-    E *= rE;
+      // advance every state by one lane step
+      E *= rE;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int kt = s / kMaxFT, f = s % kMaxFT;
+        if (kt < n_terms && f < Sh::nf(ts, kt)) advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+      }
+    t += h;
+  };
+
+  for (int k0 = 0; k0 < n_max; k0 += every) {
+    // exact re-evaluation (anchor) at the first step of the segment
+    t = fma((double)k0, h, t_first);
+    E = x_exp(neg_inv_tau * t);
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
       const int kt = s / kMaxFT, f = s % kMaxFT;
-      if (kt < n_terms && f < Sh::nf(ts, kt)) advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+      if (kt < n_terms && f < Sh::nf(ts, kt))
+        anchor(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
     }
-  }
+    const int k1 = min(n_full, k0 + every);
+#pragma unroll 2
+    for (int k = k0; k < k1; ++k) bin_step(k);  // uniform trip count
+    if (extra && k1 == n_full && n_full < k0 + every) bin_step(n_full);
   }
   if constexpr (MODE == kModeModel) return;
 
@@ -629,9 +673,17 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
   if constexpr (MODE == kModeGrad) {
 #pragma unroll
     for (int r = 0; r < kRS; ++r) {
-      if (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN) {
+      // scalars the shape cannot use are skipped at compile time for fixed shapes
+      bool used = r < 2 + kMaxT ? (r < 2 || r - 2 < n_terms) : false;
+      if (r >= kArg0) {
+        const int q = (r - kArg0) >> 1, kt = q / kMaxFT, f = q % kMaxFT, ai = (r - kArg0) & 1;
+        used = kt < n_terms && f < Sh::nf(ts, kt) && ai < prim_nargs(Sh::prim(ts, kt, f));
+      }
+      if (used && (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN)) {
         const double s = wave_sum(g[r]);
         if ((tid & 63) == 0) gred[w][r] = s;
+      } else if ((tid & 63) == 0) {
+        gred[w][r] = 0.0;
       }
     }
   }
@@ -683,7 +735,41 @@ hipError_t launch_shape(const LaunchArgs &a, int count_f64, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int COST, int MODE, typename Sh>
+int occupancy_shape(int count_f64) {
+  int nb = 0;
+  hipError_t e;
+  if (count_f64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, double, ShapeGeneric>), kBlock, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, float, Sh>), kBlock, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+template <int COST, int MODE>
+int occupancy_typed(int count_f64, int shape) {
+  switch (shape) {
+    case kShapeExpCos: return occupancy_shape<COST, MODE, ShapeExpCos>(count_f64);
+    case kShapeGaussCos: return occupancy_shape<COST, MODE, ShapeGaussCos>(count_f64);
+    case kShapeStg: return occupancy_shape<COST, MODE, ShapeStg>(count_f64);
+    case kShapeExpStg: return occupancy_shape<COST, MODE, ShapeExpStg>(count_f64);
+    case kShapeExpCosStg: return occupancy_shape<COST, MODE, ShapeExpCosStg>(count_f64);
+    default: return occupancy_shape<COST, MODE, ShapeGeneric>(count_f64);
+  }
+}
+
 }  // namespace
+
+int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape) {
+  if (mode == kModeModel) return occupancy_typed<MU_COST_CHI2, kModeModel>(count_f64, shape);
+  if (cost_kind == MU_COST_CHI2)
+    return mode == kModeGrad ? occupancy_typed<MU_COST_CHI2, kModeGrad>(count_f64, shape)
+                             : occupancy_typed<MU_COST_CHI2, kModeCost>(count_f64, shape);
+  return mode == kModeGrad ? occupancy_typed<MU_COST_POISSON, kModeGrad>(count_f64, shape)
+                           : occupancy_typed<MU_COST_POISSON, kModeCost>(count_f64, shape);
+}
 
 hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;

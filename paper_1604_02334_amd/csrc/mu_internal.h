@@ -105,6 +105,8 @@ struct LaunchArgs {
 };
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);
+// Workgroups of the evaluation kernel resident per compute unit (0 if unknown).
+int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape);
 // Merge the tile slots of jobs [0, n_jobs) of `a` (uniform or mapped).
 hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s);
 

@@ -405,57 +405,75 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
   if constexpr (MODE == kModeGrad) {
     // chain rule through the map / function array:
     //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's tiles.
-    // For a chunk of histograms the sums and the map lookups are staged in LDS
-    // (pidx >= 0: parameter index; <= -2: function -(2 + i); -1: no parameter),
-    // then thread k scans them in a fixed order.
+    // Only the scalars the theory takes from p or f are kept (list `act`). For a
+    // chunk of histograms the entries e = (hh, i) hold gR and the map lookup
+    // (pidx >= 0: parameter index; <= -2: function -(2 + i); -1: none) in LDS;
+    // then one wave per parameter gathers its entries, lane-strided, and
+    // combines them with a fixed-shape tree, so the order never depends on timing.
     constexpr int HC = 32;
-    __shared__ double gR[HC][kRS];
-    __shared__ int pidx[HC][kRS];
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double gR[HC * kRS];
+    __shared__ int pidx[HC * kRS];
+    __shared__ int act[kRS];
+    __shared__ int act_slot[kRS];
+    __shared__ int act_fun[kRS];
+    __shared__ int n_act_s;
     __shared__ double acc_s[MU_MAX_PAR];
     __shared__ double acc_c[MU_MAX_PAR];
     const DevTheory *th = J.th;
     const int n_par = th->n_par;
+    const int lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+      int n = 0;
+      for (int r = 0; r < kRS; ++r) {
+        const DevRef ref = th->rref[r];
+        if (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN) {
+          act[n] = r;
+          act_slot[n] = ref.slot;
+          act_fun[n] = ref.kind == MU_REF_FUN;
+          ++n;
+        }
+      }
+      n_act_s = n;
+    }
     for (int k = tid; k < n_par; k += kBlock) {
       acc_s[k] = 0.0;
       acc_c[k] = 0.0;
     }
+    __syncthreads();
+    const int na = n_act_s;
     for (int h0 = 0; h0 < J.n_histo; h0 += HC) {
       const int nh = min(HC, J.n_histo - h0);
-      __syncthreads();
-      for (int w = tid; w < nh * kRS; w += kBlock) {
-        const int hh = w / kRS, r = w % kRS;
+      const int ne = nh * na;
+      for (int e = tid; e < ne; e += kBlock) {
+        const int hh = e / na, i = e - hh * na;
         const int h = h0 + hh;
-        const DevRef ref = th->rref[r];
-        double s = 0.0;
-        int pi = -1;
-        if (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN) {
-          const int k0 = J.histos[h].tile0;
-          const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
-          s = sum_slots(P, k0, k1, 2 + r);
-          const int m = th->map[J.histos[h].map_row * th->n_slots + ref.slot];
-          pi = ref.kind == MU_REF_PAR ? m : -(2 + m);
-        }
-        gR[hh][r] = s;
-        pidx[hh][r] = pi;
+        const int k0 = J.histos[h].tile0;
+        const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
+        const int m = th->map[J.histos[h].map_row * th->n_slots + act_slot[i]];
+        gR[e] = sum_slots(P, k0, k1, 2 + act[i]);
+        pidx[e] = act_fun[i] ? -(2 + m) : m;
       }
       __syncthreads();
-      for (int k = tid; k < n_par; k += kBlock) {
-        Pair q{acc_s[k], acc_c[k]};
-        for (int hh = 0; hh < nh; ++hh) {
-          for (int r = 0; r < kRS; ++r) {
-            const int pi = pidx[hh][r];
-            if (pi == k) {
-              q = pair_add(q, Pair{gR[hh][r], 0.0});
-            } else if (pi <= -2) {
-              q = pair_add(q, Pair{gR[hh][r] * th->F[(int64_t)(-2 - pi) * n_par + k], 0.0});
-            }
+      for (int k = wave; k < n_par; k += kWaves) {
+        Pair q{0.0, 0.0};
+        for (int e = lane; e < ne; e += 64) {
+          const int pi = pidx[e];
+          if (pi == k) {
+            q = pair_add(q, Pair{gR[e], 0.0});
+          } else if (pi <= -2) {
+            q = pair_add(q, Pair{gR[e] * th->F[(int64_t)(-2 - pi) * n_par + k], 0.0});
           }
         }
-        acc_s[k] = q.s;
-        acc_c[k] = q.c;
+        q = wave_pair_sum(q);
+        if (lane == 0) {
+          const Pair t = pair_add(Pair{acc_s[k], acc_c[k]}, q);
+          acc_s[k] = t.s;
+          acc_c[k] = t.c;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
     for (int k = tid; k < n_par; k += kBlock) J.grad_out[k] = pair_value(Pair{acc_s[k], acc_c[k]});
   }
 }

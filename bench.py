@@ -49,6 +49,11 @@ PEAK_FP64_TOPS = 39.3
 BYTES_PER_BIN = 4         # one FP32 count streamed per bin evaluation
 
 
+def _log(*a):
+    """Progress on stderr (the JSON result line is the only stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def _workload(api, ctx):
     """The 16 x 65536 set: counts drawn from the library's own model values."""
     import synth
@@ -133,6 +138,7 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     for j, s in enumerate(sets):
         start[j, :s["start"].size] = s["start"]
     bins = sum(d.n_bins for d in datas)
+    _log(f"c4: {n_sets} datasets, {bins} bins; batched fits")
     t0 = time.perf_counter()
     pb, covb, rb = api.fit_batch(ctx, datas, ths, start)
     tb = time.perf_counter() - t0
@@ -140,6 +146,7 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     t0 = time.perf_counter()
     pb2, _, rb2 = api.fit_batch(ctx, [datas[j] for j in sub], [ths[j] for j in sub], start[sub], want_cov=False)
     tb2 = time.perf_counter() - t0
+    _log(f"c4: batched {tb:.1f} s; plain subset of {n_plain}")
     t0 = time.perf_counter()
     pp, _, rp = api.fit_batch(ctx, [datas[j] for j in sub], [ths[j] for j in sub], start[sub],
                               analytic_grad=False, batched=False, want_cov=False)
@@ -179,9 +186,11 @@ def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_p
     assert init.size == param_count()
     S = Seeder(ctx, init)
     steps = train_samples // batch
+    _log(f"c5: training {steps} steps of {batch}")
     t0 = time.perf_counter()
     curve = S.train(seed=160402334, steps=steps, batch=batch, lr=2e-3)
     t_train = time.perf_counter() - t0
+    _log(f"c5: trained in {t_train:.1f} s; generating {n_eval} fresh histograms")
     counts, theta, _ = gen_histos(ctx, seed=1604, first=0, n=n_eval, fine=True)
     h = [{"n_bins": 8192, "dt": 0.001, "t0_bin": 0.0, "first": 0, "last": 8191, "map_row": 0}]
     datas = [api.Data(ctx, h, [counts[i].astype(np.float64)]) for i in range(n_eval)]
@@ -193,15 +202,19 @@ def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_p
     # default start: the same window estimates of N0 and Nbkg, fixed A, lambda, nu, phi
     default = seeded.copy()
     default[:, 2:] = [0.175, 0.5, math.sqrt(5.0), 0.0]
+    _log("c5: fits from the true parameters")
     t0 = time.perf_counter()
     p_ref, cov, r_ref = api.fit_batch(ctx, datas, ths, theta)
     t_ref = time.perf_counter() - t0
+    _log(f"c5: {t_ref:.1f} s; fits from seeded starts")
     t0 = time.perf_counter()
     p_s, _, r_s = api.fit_batch(ctx, datas, ths, seeded, want_cov=False)
     t_s = time.perf_counter() - t0
+    _log(f"c5: {t_s:.1f} s; fits from default starts")
     t0 = time.perf_counter()
     p_d, _, r_d = api.fit_batch(ctx, datas, ths, default, want_cov=False)
     t_d = time.perf_counter() - t0
+    _log(f"c5: {t_d:.1f} s; plain subset of {n_plain}")
     sub = list(range(n_plain))
     t0 = time.perf_counter()
     p_p, _, r_p = api.fit_batch(ctx, [datas[i] for i in sub], [th] * n_plain, default[sub],
@@ -239,6 +252,9 @@ def main():
     ap.add_argument("--no-fits", action="store_true", help="skip the fit and seeder sections")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the timed stencil launches (for hardware-counter runs)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="with --stencil-only: bins per workgroup (skips the autotuner; 0 keeps it)")
+    ap.add_argument("--anchor", type=int, default=0, help="with --stencil-only and --tile: anchor interval")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -269,19 +285,25 @@ def main():
     p_dev = torch.tensor(p0[None], dtype=torch.float64, device=dev)
     s_dev = torch.tensor(stencil, dtype=torch.float64, device=dev)
     st = ctx.torch_stream
+    torch.cuda.synchronize()
+    # every launch of the step goes to the context's stream: no cross-stream events
+    stream_ctx = torch.cuda.stream(st)
+    stream_ctx.__enter__()
 
-    def step(ev=None):
+    def step():
         api.chi2_grad(ctx, data, th, p_dev)
-        if ev is not None:
-            ev[0].record(st)
-        c = api.chi2_eval(ctx, data, th, s_dev)
-        if ev is not None:
-            ev[1].record(st)
-        return c
+        return api.chi2_eval(ctx, data, th, s_dev)
 
-    # measured tile / anchor choice for both launches (untimed)
-    tune_eval = api.autotune(ctx, data, th, s_dev)
-    tune_grad = api.autotune(ctx, data, th, p_dev, grad=True)
+    if args.stencil_only and args.tile:
+        # a fixed launch configuration (hardware-counter runs): no candidate launches
+        ctx.tile = args.tile
+        if args.anchor:
+            ctx.anchor = args.anchor
+        tune_eval = (args.tile, ctx.anchor)
+    else:
+        # measured tile / anchor choice for both launches (untimed)
+        tune_eval = api.autotune(ctx, data, th, s_dev)
+        tune_grad = api.autotune(ctx, data, th, p_dev, grad=True)
     if args.stencil_only:
         for _ in range(args.steps):
             api.chi2_eval(ctx, data, th, s_dev)
@@ -293,14 +315,24 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    # Kernel durations: the same K steps again with HIP events recorded by the
+    # library around each launch on its stream (an event pair adds a few
+    # microseconds between launches, so the wall-clock pass above runs without)
+    ctx.timing(True)
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    n_cost, ms_cost = ctx.timing_read("cost")
+    n_grad, ms_grad = ctx.timing_read("grad")
+    n_merge, ms_merge = ctx.timing_read("merge")
+    assert n_cost == args.steps and n_grad == args.steps and n_merge == 2 * args.steps
 
     # single-vector latency (cost only, host in and out)
     host_p = p0[None]
@@ -314,7 +346,7 @@ def main():
     bins_per_step = (1 + stencil.shape[0]) * n_bins
     ms_per_step = wall / args.steps * 1e3
     value = bins_per_step / (wall / args.steps) / 1e9
-    k_ms = float(np.mean(kern_ms))
+    k_ms = ms_cost / n_cost
     k_bins = stencil.shape[0] * n_bins
     achieved = FLOPS_PER_BIN_CHI2 * k_bins / (k_ms * 1e-3) / 1e12
     out = {
@@ -341,12 +373,17 @@ def main():
                   "fp64_op_issue_frac": round(OPS_PER_BIN_CHI2 * k_bins / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TOPS, 4),
                   "tuned_stencil": {"tile": tune_eval[0], "anchor": tune_eval[1]},
                   "tuned_grad": {"tile": tune_grad[0], "anchor": tune_grad[1]},
+                  "grad_kernel_us": round(ms_grad / n_grad * 1e3, 2),
+                  "merge_kernels_us_per_step": round(ms_merge / args.steps * 1e3, 2),
                   "single_eval_host_latency_us": round(lat_us, 2)},
     }
+    stream_ctx.__exit__(None, None, None)
+    _log(f"step: {value:.1f} Gbin/s")
     if not args.no_fits:
         out["fits_c4"] = _fits_c4(api, ctx)
         out["seeder_c5"] = _seeder_c5(api, ctx)
     if not args.no_cpu:
+        _log("cpu baseline (oracle)")
         out["cpu_baseline"] = _cpu_baseline(cfg, counts, stencil)
     print(json.dumps(out), flush=True)
     ctx.close()

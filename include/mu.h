@@ -201,20 +201,27 @@ mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data,
 mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
                         const double *params, unsigned mem, double *out);
 
-/* Tile size (bins per workgroup) used by evaluation launches on this
- * context.  0 (default): per launch, the choice mu_autotune measured for the
- * same theory shape, mode, cost and size (to a power of two), else about four
- * workgroups per compute unit with tiles of 1024 .. 65536 bins.  Otherwise a
- * multiple of 256 in [256, 65536].  Results depend on it only through the
+/* Bins per workgroup used by evaluation launches on this context.
+ * Single-dataset launches (mu_chi2_eval, mu_chi2_grad, mu_model_eval) cut the
+ * n_vec x bins work into equal ranges of this many bins, one per workgroup,
+ * across histogram and vector boundaries; batched launches (mu_chi2_batch,
+ * the fitter) cut each histogram into tiles of this size.  0 (default): per
+ * launch, the choice mu_autotune measured for the same theory shape, mode,
+ * cost and size (to a power of two), else for single-dataset launches one
+ * range per resident workgroup (at least 256 bins) and for batched launches
+ * about four workgroups per compute unit with tiles of 1024 .. 65536 bins.
+ * Otherwise any value in [256, 2^26].  Results depend on it only through the
  * rounding order of the sums. */
 mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins);
 int32_t mu_ctx_get_tile(const mu_ctx *ctx);
 
 /* Lane steps between exact re-evaluations of the theory's factors (the rest
- * are advanced by exact recurrences of the uniform time grid): 1 evaluates
- * every bin directly; 0 restores the default (64).  Range [1, 256]; the
- * recurrence drift of a factor grows like k eps (geometric, rotation) and
- * k^2 eps / 2 (Gaussian): below 5e-13 relative at 64 and 8e-12 at 256. */
+ * are advanced by exact recurrences of the uniform time grid); 0 restores the
+ * default (64).  Range [1, 256], rounded up to a multiple of 4 lane steps
+ * (the distance at which counts are read ahead of their use), so 1 .. 4 all
+ * re-evaluate every fourth step.  The recurrence drift of a factor grows like
+ * k eps (geometric, rotation) and k^2 eps / 2 (Gaussian): below 5e-13
+ * relative at 64 and 8e-12 at 256. */
 mu_status mu_ctx_set_anchor(mu_ctx *ctx, int32_t every);
 int32_t mu_ctx_get_anchor(const mu_ctx *ctx);
 
@@ -224,10 +231,30 @@ int32_t mu_ctx_get_anchor(const mu_ctx *ctx);
  * to rounding either way. */
 mu_status mu_ctx_set_specialize(mu_ctx *ctx, int32_t on);
 
+/* Kernel timing.  While enabled, the context records a pair of HIP events on
+ * its stream around every evaluation-kernel and merge-kernel launch it makes
+ * (mu_chi2_eval, mu_chi2_grad, mu_chi2_batch, mu_model_eval, the fitter).
+ * enable != 0 discards earlier records and starts recording; enable == 0
+ * stops (records are kept).  Events are reused across enables; they are the
+ * only cost, and launches are not otherwise changed. */
+typedef enum {
+  MU_TIME_EVAL_COST = 0,  /* evaluation kernels, cost only */
+  MU_TIME_EVAL_GRAD = 1,  /* evaluation kernels, cost and gradient */
+  MU_TIME_EVAL_MODEL = 2, /* mu_model_eval kernels */
+  MU_TIME_MERGE = 3       /* merge kernels (both modes) */
+} mu_time_kind;
+mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable);
+/* Waits for the recorded launches of `kind` to finish and writes how many
+ * there were and their summed duration in milliseconds (start event to end
+ * event on the stream).  MU_E_ARG for an unknown kind or NULL outputs. */
+mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_launches, double *total_ms);
+
 /* Measure the evaluation of n_vec vectors over `data` (cost, or cost and
- * gradient when grad != 0) for tile sizes 1024 .. 65536 and anchor intervals
- * 32 .. 256, keep candidates whose costs agree with the first to 1e-12
- * relative, and remember the fastest for later launches of the same theory
+ * gradient when grad != 0) for several bins-per-workgroup values (powers of
+ * two from 1024 to 65536, and the values that give 1, 2, 3, 4, 6 or 8
+ * workgroups per resident slot) and anchor intervals 32 .. 256, keep
+ * candidates whose costs agree with the first to 1e-12 relative, and
+ * remember the fastest for later single-dataset launches of the same theory
  * shape, mode, cost and size (to a power of two) while the tile size is 0.
  * Writes the choice and its time per launch in microseconds (any may be
  * NULL).  Leaves the explicit tile size and anchor interval unchanged. */

@@ -81,14 +81,35 @@ class Context:
     def set_specialize(self, on):
         _check(A.lib().mu_ctx_set_specialize(self.h, 1 if on else 0), self.h, "mu_ctx_set_specialize")
 
-    # ordering with torch's current stream for device tensors
+    def timing(self, on):
+        """Start (discarding earlier records) or stop event timing of kernel launches."""
+        _check(A.lib().mu_ctx_timing(self.h, 1 if on else 0), self.h, "mu_ctx_timing")
+
+    _TIME_KINDS = {"cost": 0, "grad": 1, "model": 2, "merge": 3}
+
+    def timing_read(self, kind):
+        """(launch count, summed milliseconds) of the recorded launches of `kind`
+        ('cost', 'grad', 'model' or 'merge')."""
+        n = C.c_int32()
+        ms = C.c_double()
+        _check(A.lib().mu_ctx_timing_read(self.h, self._TIME_KINDS[kind], C.byref(n), C.byref(ms)), self.h,
+               "mu_ctx_timing_read")
+        return n.value, ms.value
+
+    # Ordering with torch's current stream for device tensors. A caller that
+    # already runs on the context's stream (``with torch.cuda.stream(ctx.torch_stream)``)
+    # needs no cross-stream event: work on one stream is ordered by itself.
     def _enter_device(self):
         import torch
         cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream == self.torch_stream.cuda_stream:
+            return None
         self.torch_stream.wait_stream(cur)
         return cur
 
     def _leave_device(self, cur, tensors):
+        if cur is None:
+            return
         cur.wait_stream(self.torch_stream)
         for t in tensors:
             if t is not None:

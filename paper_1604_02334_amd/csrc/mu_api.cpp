@@ -168,6 +168,7 @@ extern "C" mu_status mu_ctx_destroy(mu_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   ctx->release_all();
   if (ctx->staging_free) hipEventDestroy(ctx->staging_free);
+  for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   delete ctx;
   return MU_OK;
@@ -181,6 +182,56 @@ void mu_ctx::release_all() {
   staging.release();
   staging_out.release();
   for (auto &b : extra) b.release();
+}
+
+int mu_ctx::time_begin(int kind) {
+  if (!timing) return -1;
+  const size_t need = 2 * (timed.size() + 1);
+  while (ev_pool.size() < need) {
+    hipEvent_t ev;
+    // timing-only events: no system-scope fence (cache write-back) at each record
+    if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) return -1;  // best effort
+    ev_pool.push_back(ev);
+  }
+  Timed t{kind, ev_pool[need - 2], ev_pool[need - 1]};
+  if (hipEventRecord(t.a, stream) != hipSuccess) return -1;
+  timed.push_back(t);
+  return (int)timed.size() - 1;
+}
+
+void mu_ctx::time_end(int idx) {
+  if (idx >= 0) hipEventRecord(timed[idx].b, stream);
+}
+
+extern "C" mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable) {
+  if (!ctx) return MU_E_ARG;
+  if (enable) ctx->timed.clear();
+  ctx->timing = enable != 0;
+  return MU_OK;
+}
+
+extern "C" mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_launches, double *total_ms) {
+  if (!ctx) return MU_E_ARG;
+  if (kind < MU_TIME_EVAL_COST || kind > MU_TIME_MERGE || !n_launches || !total_ms) {
+    set_err(ctx, "mu_ctx_timing_read: unknown kind %d or NULL output", kind);
+    return MU_E_ARG;
+  }
+  hipSetDevice(ctx->device);
+  int32_t n = 0;
+  double tot = 0.0;
+  for (const auto &t : ctx->timed) {
+    if (t.kind != kind) continue;
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+    tot += ms;
+    ++n;
+  }
+  *n_launches = n;
+  *total_ms = tot;
+  return MU_OK;
 }
 
 extern "C" const char *mu_ctx_last_error(const mu_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -198,8 +249,8 @@ extern "C" mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins) {
     ctx->tile_bins = 0;
     return MU_OK;
   }
-  if (tile_bins < kBlock || tile_bins > 65536 || tile_bins % kBlock) {
-    set_err(ctx, "tile_bins must be a multiple of %d in [%d, 65536]", kBlock, kBlock);
+  if (tile_bins < kBlock || tile_bins > kMaxSplit) {
+    set_err(ctx, "tile_bins must be 0 or in [%d, %d]", kBlock, kMaxSplit);
     return MU_E_ARG;
   }
   ctx->tile_bins = tile_bins;
@@ -330,6 +381,8 @@ mu_status mu_data::tiles(int tile_bins, const TileSet **out) {
 void mu_data::free_dev() {
   if (counts) hipFree(counts);
   counts = nullptr;
+  if (d_hh) hipFree(d_hh);
+  d_hh = nullptr;
   for (TileSet &t : sets) {
     if (t.d_tiles) hipFree(t.d_tiles);
     if (t.d_histos) hipFree(t.d_histos);
@@ -340,12 +393,35 @@ void mu_data::free_dev() {
 // Tile size for a launch: the tuned choice for this (shape, mode, cost, size)
 // if one was measured, else about four workgroups per compute unit with
 // tiles of 1024 .. 65536 bins.
+// Key of the tuned table: theory shape, mode, cost, launch kind (tile or
+// split) and the size of the launch to a power of two.
+static int tune_key(int shape, int mode, int cost, int split, int64_t work) {
+  int lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= work) ++lg;
+  return (((shape * 4 + mode) * 2 + cost) * 2 + split) * 64 + lg;
+}
+
+int64_t mu_ctx::pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const {
+  *anchor = anchor_every;
+  if (tile_bins > 0) return tile_bins;
+  const int key = tune_key(shape, mode, cost, 1, work);
+  for (const Tuned &t : tuned)
+    if (t.key == key) {
+      *anchor = t.anchor;
+      return t.tile;
+    }
+  // one range per resident workgroup of the cost kernel (the same ranges for
+  // the cost and the gradient pass, so their costs agree bit for bit), at
+  // least one bin per lane
+  const int per_cu = eval_blocks_per_cu(kModeCost, cost, count_f64, shape);
+  const int64_t cap = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
+  return std::max<int64_t>(kBlock, (work + cap - 1) / cap);
+}
+
 int mu_ctx::pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const {
   *anchor = anchor_every;
   if (tile_bins > 0) return tile_bins;
-  int lg = 0;
-  while (((int64_t)1 << (lg + 1)) <= work) ++lg;
-  const int key = ((shape * 4 + mode) * 2 + cost) * 64 + lg;
+  const int key = tune_key(shape, mode, cost, 0, work);
   for (const Tuned &t : tuned)
     if (t.key == key) {
       *anchor = t.anchor;
@@ -391,9 +467,9 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
   }
   d->total = total;
   const size_t esz = d->f64 ? sizeof(double) : sizeof(float);
-  // one lane step (256 values) of zero padding: kernels read each lane's next
-  // count one step ahead, and the read after a lane's last bin lands here
-  const size_t padded = ((size_t)total + kBlock) * esz;
+  // kPrefetch lane steps (of 256 values) of zero padding: kernels read each
+  // lane's counts that many steps ahead, and reads past the last bin land here
+  const size_t padded = ((size_t)total + (size_t)kPrefetch * kBlock) * esz;
   hipError_t e = hipMalloc(&d->counts, padded);
   if (e != hipSuccess) {
     delete d;
@@ -415,6 +491,8 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
     }
     e = hipMemcpy(d->counts, buf.data(), buf.size(), hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess) e = hipMalloc(&d->d_hh, d->hh.size() * sizeof(DevHisto));
+  if (e == hipSuccess) e = hipMemcpy(d->d_hh, d->hh.data(), d->hh.size() * sizeof(DevHisto), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     d->free_dev();
     delete d;
@@ -740,12 +818,11 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   hipSetDevice(ctx->device);
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
   int anchor = ctx->anchor_every;
-  const int tile = ctx->pick_tile(shape, mode, cost_kind, (int64_t)n_vec * d->total, d->longest, &anchor);
-  const TileSet *ts = nullptr;
-  if ((st = d->tiles(tile, &ts)) != MU_OK) return st;
+  const int64_t work = (int64_t)n_vec * d->total;
+  const int64_t W = ctx->pick_split(shape, mode, cost_kind, d->f64, work, &anchor);
   const int n_par = th->h.n_par;
-  const int64_t n_blocks = (int64_t)n_vec * ts->n_tiles;
-  if (n_blocks > INT32_MAX) {
+  const int64_t n_blocks = (work + W - 1) / W;
+  if (n_blocks + (int64_t)n_vec * d->n_histo > INT32_MAX) {
     set_err(ctx, "launch needs more than 2^31 workgroups");
     return MU_E_UNSUPPORTED;
   }
@@ -775,20 +852,22 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
     dm = n_m ? o + n_c + n_h + n_g : nullptr;
   }
   if (mode != kModeModel) {
-    if ((st = ctx->partial.ensure(ctx, (size_t)n_blocks * kSlot * sizeof(double), false)) != MU_OK) return st;
+    // slot b + v * n_histo + h for every segment (see the split launch)
+    const size_t n_slots = (size_t)n_blocks + (size_t)n_vec * d->n_histo;
+    if ((st = ctx->partial.ensure(ctx, n_slots * kSlot * sizeof(double), false)) != MU_OK) return st;
   }
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.tmpl.th = th->d_th;
-  a.tmpl.histos = ts->d_histos;
+  a.tmpl.histos = d->d_hh;
   a.tmpl.counts = d->counts;
-  a.tmpl.tiles = ts->d_tiles;
+  a.tmpl.tiles = nullptr;
   a.tmpl.p = dp;
   a.tmpl.cost_out = dc;
   a.tmpl.histo_out = dh;
   a.tmpl.grad_out = dg;
   a.tmpl.model_out = dm;
-  a.tmpl.n_tiles = ts->n_tiles;
+  a.tmpl.n_tiles = 0;
   a.tmpl.n_histo = d->n_histo;
   a.p_stride = n_par;
   a.grad_stride = n_par;
@@ -798,11 +877,20 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   a.n_blocks = (int32_t)n_blocks;
   a.cost_kind = cost_kind;
   a.anchor_every = anchor;
+  a.n_vec = n_vec;
+  a.split_w = W;
+  a.total = d->total;
   a.partial = static_cast<double *>(ctx->partial.ptr);
+  int ti = ctx->time_begin(mode == kModeGrad ? MU_TIME_EVAL_GRAD
+                           : mode == kModeModel ? MU_TIME_EVAL_MODEL
+                                                : MU_TIME_EVAL_COST);
   e = launch_eval(a, mode, d->f64, shape, ctx->stream);
+  ctx->time_end(ti);
   if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
   if (mode != kModeModel) {
+    ti = ctx->time_begin(MU_TIME_MERGE);
     e = launch_merge(a, mode, n_vec, ctx->stream);
+    ctx->time_end(ti);
     if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
   }
   if (mem == MU_MEM_HOST) {
@@ -997,7 +1085,9 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     a.cost_kind = cost_kind;
     a.anchor_every = ctx->anchor_every;
     a.partial = static_cast<double *>(ctx->partial.ptr);
+    const int ti = ctx->time_begin(grad ? MU_TIME_EVAL_GRAD : MU_TIME_EVAL_COST);
     e = launch_eval(a, grad ? kModeGrad : kModeCost, data[0]->f64, shp, ctx->stream);
+    ctx->time_end(ti);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched evaluation launch");
   }
   {
@@ -1005,7 +1095,9 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     std::memset(&m, 0, sizeof m);
     m.jobs = reinterpret_cast<const DevJob *>(dup);
     m.partial = static_cast<double *>(ctx->partial.ptr);
+    const int ti = ctx->time_begin(MU_TIME_MERGE);
     e = launch_merge(m, grad ? kModeGrad : kModeCost, n_jobs, ctx->stream);
+    ctx->time_end(ti);
     if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
   }
   if (mem == MU_MEM_HOST) {
@@ -1057,37 +1149,29 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   const int saved_tile = ctx->tile_bins, saved_anchor = ctx->anchor_every;
   std::vector<double> ref(n_vec), cur(n_vec);
   bool have_ref = false;
-  int bt = 0, ba = 0;
+  int64_t bt = 0;
+  int ba = 0;
   float best = 1e30f;
-  // candidates: powers of two, and tiles that split every histogram into m
-  // near-equal parts with the workgroup count just below a whole number of
-  // waves of resident workgroups (the last wave of a launch is otherwise
-  // partly idle)
-  std::vector<int> cand;
-  for (int tile = kMinTile; tile <= kMaxTile; tile *= 2) {
-    if (tile / 2 >= d->longest && tile > kMinTile) break;
-    cand.push_back(tile);
-  }
+  // candidates (bins per workgroup of the split launch): whole multiples of
+  // the resident workgroup count (every workgroup of a round equally loaded),
+  // and powers of two
+  std::vector<int64_t> cand;
+  const int64_t work_all = (int64_t)n_vec * d->total;
   {
     const int shape = ctx->specialize ? th->shape : kShapeGeneric;
     const int per_cu = eval_blocks_per_cu(mode, cost_kind, d->f64, shape);
     const int64_t cap = (int64_t)std::max(per_cu, 1) * std::max(ctx->n_cu, 1);
-    for (int m = 1; m <= 64; ++m) {
-      int tile = (int)(((d->longest + m - 1) / m + kBlock - 1) / kBlock * kBlock);
-      if (tile < kMinTile || tile > kMaxTile) continue;
-      int64_t blocks = 0;
-      for (const DevHisto &x : d->hh) blocks += (x.n + tile - 1) / tile;
-      blocks *= n_vec;
-      const int64_t waves = (blocks + cap - 1) / cap;
-      if ((double)blocks / (double)(waves * cap) >= 0.9 &&
-          std::find(cand.begin(), cand.end(), tile) == cand.end())
-        cand.push_back(tile);
+    for (int m : {1, 2, 3, 4, 6, 8}) {
+      const int64_t w = std::max<int64_t>(kBlock, (work_all + m * cap - 1) / (m * cap));
+      if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
     }
+    for (int64_t w = kMinTile; w <= kMaxTile && w < work_all; w *= 2)
+      if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
   }
   for (size_t ci = 0; ci < cand.size() && st == MU_OK; ++ci) {
-    const int tile = cand[ci];
+    const int64_t tile = cand[ci];
     for (int anchor : {32, 64, 128, 256}) {
-      ctx->tile_bins = tile;
+      ctx->tile_bins = (int)tile;
       ctx->anchor_every = anchor;
       for (int w = 0; w < 2 && st == MU_OK; ++w)
         st = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
@@ -1131,19 +1215,16 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   }
   // remember the choice for launches of this shape, mode, cost and size
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
-  const int64_t work = (int64_t)n_vec * d->total;
-  int lg = 0;
-  while (((int64_t)1 << (lg + 1)) <= work) ++lg;
-  const int key = ((shape * 4 + mode) * 2 + cost_kind) * 64 + lg;
+  const int key = tune_key(shape, mode, cost_kind, 1, work_all);
   bool found = false;
   for (auto &t : ctx->tuned)
     if (t.key == key) {
-      t.tile = bt;
+      t.tile = (int)bt;
       t.anchor = ba;
       found = true;
     }
-  if (!found) ctx->tuned.push_back({key, bt, ba});
-  if (best_tile) *best_tile = bt;
+  if (!found) ctx->tuned.push_back({key, (int)bt, ba});
+  if (best_tile) *best_tile = (int32_t)bt;
   if (best_anchor) *best_anchor = ba;
   if (best_us) *best_us = best / 5.0 * 1e3;
   return MU_OK;

@@ -67,6 +67,7 @@ struct TStruct {
 
 struct ShapeGeneric {
   static constexpr bool kFixed = false;
+  static constexpr bool kScalable = false;
   __device__ static int nt(const TStruct &ts) { return ts.nt; }
   __device__ static int nf(const TStruct &ts, int k) { return ts.nf[k]; }
   __device__ static int prim(const TStruct &ts, int k, int f) { return ts.prim[k][f]; }
@@ -75,6 +76,15 @@ struct ShapeGeneric {
 template <int NT, int NF0, int P00, int P01, int NF1, int P10, int P11>
 struct ShapeFixed {
   static constexpr bool kFixed = true;
+  // Cost and model passes may fold N0, the lifetime and each term's weight
+  // into the state of the term's first factor when that factor follows a
+  // linear recurrence (se, sg, tf) or is a lone stg (its constant part then
+  // joins the lifetime state); no ge anywhere (ge needs t itself).
+  static constexpr bool lead_ok(int p, int nf) {
+    return p == MU_SE || p == MU_SG || p == MU_TF || (p == MU_STG && nf == 1);
+  }
+  static constexpr bool kScalable = lead_ok(P00, NF0) && (NT < 2 || lead_ok(P10, NF1)) && P00 != MU_GE &&
+                                    P01 != MU_GE && P10 != MU_GE && P11 != MU_GE;
   __device__ static constexpr int nt(const TStruct &) { return NT; }
   __device__ static constexpr int nf(const TStruct &, int k) { return k == 0 ? NF0 : (k == 1 ? NF1 : 0); }
   __device__ static constexpr int prim(const TStruct &, int k, int f) {
@@ -127,6 +137,27 @@ __device__ __forceinline__ double bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), src);
   const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wave-uniform copies of values that are the same in every lane (scalar
+// registers): for loads the compiler cannot prove uniform, e.g. after the
+// workgroup has written memory that might alias them.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double(uni((int64_t)__double_as_longlong(v))); }
+__device__ __forceinline__ DevHisto uni(DevHisto x) {
+  x.off = uni(x.off);
+  x.n = uni(x.n);
+  x.first = uni(x.first);
+  x.t0_bin = uni(x.t0_bin);
+  x.dt = uni(x.dt);
+  x.map_row = uni(x.map_row);
+  x.tile0 = uni(x.tile0);
+  return x;
 }
 
 // Out-of-line transcendentals: they run at anchors and in the workgroup
@@ -375,15 +406,53 @@ __device__ double sum_slot_pairs(const double *P, int k0, int k1) {
 }
 
 // Merge the tile slots of job J in a fixed order and write its outputs.
+// Slots of one job: per histogram a contiguous range, and the span of all of
+// them (tile launch: the job's tile table; split launch: workgroup + histogram
+// index of each segment).
+struct SlotMap {
+  const double *P;
+  const DevJob *J;
+  int64_t W, vbase;  // split launch: bins per workgroup, first bin of the vector
+  int jbase;         // split launch: v * n_histo
+  __device__ void range(int h, int &k0, int &k1) const {
+    if (W == 0) {
+      k0 = J->histos[h].tile0;
+      k1 = (h + 1 < J->n_histo) ? J->histos[h + 1].tile0 : J->n_tiles;
+    } else {
+      const int64_t s = vbase + J->histos[h].off;
+      k0 = (int)(jbase + h + s / W);
+      k1 = (int)(jbase + h + (s + J->histos[h].n - 1) / W) + 1;
+    }
+  }
+  __device__ void span(int &k0, int &k1) const {
+    if (W == 0) {
+      k0 = 0;
+      k1 = J->n_tiles;
+    } else {
+      int t;
+      range(0, k0, t);
+      range(J->n_histo - 1, t, k1);
+    }
+  }
+};
+
 template <int MODE>
-__device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
+__device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   __shared__ Pair red[kBlock / 64];
   const int tid = threadIdx.x;
-  const double *P = a.partial + (int64_t)J.tile_base * kSlot;
+  SlotMap sm;
+  sm.J = &J;
+  sm.W = (a.jobs == nullptr) ? a.split_w : 0;
+  sm.P = sm.W ? a.partial : a.partial + (int64_t)J.tile_base * kSlot;
+  sm.vbase = (int64_t)job * a.total;
+  sm.jbase = job * J.n_histo;
+  const double *P = sm.P;
+  int s0, s1;
+  sm.span(s0, s1);
 
-  // total cost: strided fixed assignment of tiles to threads, then a tree
+  // total cost: strided fixed assignment of slots to threads, then a tree
   Pair acc{0.0, 0.0};
-  for (int k = tid; k < J.n_tiles; k += kBlock) acc = pair_add(acc, Pair{P[k * kSlot], P[k * kSlot + 1]});
+  for (int k = s0 + tid; k < s1; k += kBlock) acc = pair_add(acc, Pair{P[(int64_t)k * kSlot], P[(int64_t)k * kSlot + 1]});
   acc = wave_pair_sum(acc);
   if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
@@ -396,8 +465,8 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
   // per-histogram cost
   if (J.histo_out) {
     for (int h = tid; h < J.n_histo; h += kBlock) {
-      const int k0 = J.histos[h].tile0;
-      const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
+      int k0, k1;
+      sm.range(h, k0, k1);
       J.histo_out[h] = sum_slot_pairs(P, k0, k1);
     }
   }
@@ -423,18 +492,20 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
     const DevTheory *th = J.th;
     const int n_par = th->n_par;
     const int lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) {
-      int n = 0;
-      for (int r = 0; r < kRS; ++r) {
-        const DevRef ref = th->rref[r];
-        if (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN) {
-          act[n] = r;
-          act_slot[n] = ref.slot;
-          act_fun[n] = ref.kind == MU_REF_FUN;
-          ++n;
-        }
+    if (wave == 0) {
+      // compaction in order of r: lane r keeps its scalar at the rank of r
+      // among the active ones
+      DevRef ref{};
+      if (lane < kRS) ref = th->rref[lane];
+      const bool on = lane < kRS && (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN);
+      const unsigned long long mask = __ballot(on);
+      if (on) {
+        const int at = __popcll(mask & ((1ull << lane) - 1ull));
+        act[at] = lane;
+        act_slot[at] = ref.slot;
+        act_fun[at] = ref.kind == MU_REF_FUN;
       }
-      n_act_s = n;
+      if (lane == 0) n_act_s = __popcll(mask);
     }
     for (int k = tid; k < n_par; k += kBlock) {
       acc_s[k] = 0.0;
@@ -448,8 +519,8 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
       for (int e = tid; e < ne; e += kBlock) {
         const int hh = e / na, i = e - hh * na;
         const int h = h0 + hh;
-        const int k0 = J.histos[h].tile0;
-        const int k1 = (h + 1 < J.n_histo) ? J.histos[h + 1].tile0 : J.n_tiles;
+        int k0, k1;
+        sm.range(h, k0, k1);
         const int m = th->map[J.histos[h].map_row * th->n_slots + act_slot[i]];
         gR[e] = sum_slots(P, k0, k1, 2 + act[i]);
         pidx[e] = act_fun[i] ? -(2 + m) : m;
@@ -480,16 +551,26 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J) {
 
 // ------------------------------------------------------------------- kernel
 
+// What one segment needs: bins [begin, begin + n) of one histogram's fit
+// range (first bin `first` of the histogram, counts from `off` in the
+// concatenated counts), evaluated for the parameter vector p; the workgroup's
+// cost (and gradient) partials go to its slot.
+struct SegIn {
+  const DevTheory *th;
+  const double *p;
+  const void *counts;
+  double *model_out;
+  int64_t off, first, begin;
+  double t0_bin, dt;
+  int32_t map_row, n, anchor_every;
+};
+
+// One segment (see SegIn).
 template <int COST, int MODE, typename CT, typename Sh>
-__global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   const int tid = threadIdx.x;
-  int job;
-  const DevJob J = job_of(a, b, job);
-  const DevTile T = J.tiles[b - J.block_base];
-  const DevHisto H = J.histos[T.histo];
-  const DevTheory *th = J.th;
-  const int row = H.map_row;
+  const DevTheory *th = S.th;
+  const int row = S.map_row;
   TStruct ts;
   if constexpr (!Sh::kFixed) {
     ts.nt = __builtin_amdgcn_readfirstlane(th->n_terms);
@@ -511,12 +592,12 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
   // resolves scalar r, then each is broadcast to scalar registers
   double R[kRS];
   {
-    const double mine = lane < kRS ? resolve_ref(th, th->rref[lane], J.p, row) : 0.0;
+    const double mine = lane < kRS ? resolve_ref(th, th->rref[lane], S.p, row) : 0.0;
 #pragma unroll
     for (int r = 0; r < kRS; ++r) R[r] = bcast(mine, r);
   }
   const double n0 = R[0], nbkg = R[1];
-  const double h = H.dt * (double)kBlock;  // lane step
+  const double h = S.dt * (double)kBlock;  // lane step
 
   // uniform step constants, one transcendental per lane of every wave, then
   // broadcast within the wave: lane 0: lifetime ratio; lane 1 + 2 s + w:
@@ -546,44 +627,111 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
     c1[s] = bcast(cst, 2 + 2 * s);
   }
 
+  // Scaled cost / model pass. N = N0 e^(-t/tau) (1 + sum_k w_k prod_f F_kf) +
+  // Nbkg with w_k = coef_k amp_k is evaluated as
+  //   N = E + Nbkg + sum_k L_k prod_{f>0} F_kf,
+  // where L_k = N0 w_k e^(-t/tau) F_k0 is the scaled state of the term's
+  // first factor (all its recurrences are linear: the lifetime ratio joins its
+  // step constants), and E = N0 (1 + sum of w_k / 3 over lone-stg terms)
+  // e^(-t/tau) carries the constant part of lone stg terms. stg factors keep
+  // (2/3) g in their Gaussian state and u = sigma t as a state of their own.
+  constexpr bool kScaled = MODE != kModeGrad && Sh::kScalable;
+  double ecoef = n0;  // E = ecoef e^(-t/tau)
+  double su[kSlots];  // sigma h for stg slots
+  if constexpr (kScaled) {
+#pragma unroll
+    for (int kt = 0; kt < kMaxT; ++kt) {
+      if (kt < n_terms) {
+        const int s = kt * kMaxFT;
+        const int p = Sh::prim(ts, kt, 0);
+        if (p == MU_SE) c0[s] *= rE;
+        if (p == MU_TF) {
+          c0[s] *= rE;
+          c1[s] *= rE;
+        }
+        if (p == MU_STG) ecoef = fma(n0 * (coef[kt] * R[2 + kt]), kThird, ecoef);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) su[s] = R[kArg0 + 2 * s] * h;
+  }
+
   // per-lane states
   double E = 0.0;
-  double s0[kSlots], s1[kSlots];
+  double s0[kSlots], s1[kSlots], u[kSlots];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) s0[s] = s1[s] = 0.0;
+  for (int s = 0; s < kSlots; ++s) s0[s] = s1[s] = u[s] = 0.0;
 
   double lane_cost = 0.0;
   double g[kRS];
 #pragma unroll
   for (int r = 0; r < kRS; ++r) g[r] = 0.0;
 
-  const int64_t n_first = H.first + T.begin + tid;  // this lane's first bin
-  const double t_first = ((double)n_first - H.t0_bin) * H.dt;
-  // every lane has n_full bins; lanes below T.n % 256 have one more
-  const int n_full = T.n / kBlock;
-  const bool extra = tid < (T.n % kBlock);
-  const int n_max = n_full + ((T.n % kBlock) != 0 ? 1 : 0);  // uniform
+  const int64_t n_first = S.first + S.begin + tid;  // this lane's first bin
+  const double t_first = ((double)n_first - S.t0_bin) * S.dt;
+  // every lane has n_full bins; lanes below S.n % 256 have one more
+  const int seg_n = __builtin_amdgcn_readfirstlane(S.n);  // wave-uniform: scalar loop control
+  const int n_full = seg_n / kBlock;
+  const bool extra = tid < (seg_n % kBlock);
+  const int n_max = n_full + ((seg_n % kBlock) != 0 ? 1 : 0);
   // FP32 storage holds integer counts only (the host checks), FP64 any value
   constexpr bool kIntData = sizeof(CT) == 4;
-  // counts are read one step ahead of their use so the load latency overlaps
-  // the theory evaluation of the current bin; the read after a lane's last
-  // bin stays inside the counts buffer, which the host pads by one step
-  const int64_t idx0 = H.off + T.begin + tid;
-  const CT *cp = static_cast<const CT *>(J.counts) + idx0;
-  double d_next = 0.0;
-  if constexpr (MODE != kModeModel) d_next = (double)cp[0];
-  const int every = a.anchor_every;
+  // Counts are read kPrefetch lane steps ahead of their use, into a ring of
+  // registers: dq[i] holds the count of the next step k with k % kPrefetch ==
+  // i. Reads past a lane's last bin stay inside the counts buffer, which the
+  // host pads by kPrefetch steps. Values stay in the storage type until use.
+  const int64_t idx0 = S.off + S.begin + tid;
+  typedef const __attribute__((address_space(1))) CT *GlobalCT;  // global loads, not flat
+  const GlobalCT cp = (GlobalCT)(static_cast<const CT *>(S.counts) + idx0);
+  CT dq[kPrefetch];
+#pragma unroll
+  for (int i = 0; i < kPrefetch; ++i) dq[i] = CT(0);
+  if constexpr (MODE != kModeModel) {
+#pragma unroll
+    for (int i = 0; i < kPrefetch; ++i) dq[i] = cp[(int64_t)i * kBlock];
+  }
+  // anchors at multiples of kPrefetch steps keep the ring aligned
+  const int every = (S.anchor_every + kPrefetch - 1) / kPrefetch * kPrefetch;
   double t = t_first;
 
   // one bin: value, cost term (or model value), gradient, then advance
-  auto bin_step = [&](int k) {
+  auto bin_step = [&](int k, double d_cur) {
     const int64_t idx = idx0 + (int64_t)k * kBlock;
-    double d_cur = 0.0;
-    if constexpr (MODE != kModeModel) {
-      d_cur = d_next;
-      d_next = (double)cp[(int64_t)(k + 1) * kBlock];
-    }
-      if constexpr (MODE != kModeGrad) {
+      if constexpr (kScaled) {
+        double acc = E + nbkg;
+#pragma unroll
+        for (int kt = 0; kt < kMaxT; ++kt) {
+          if (kt < n_terms) {
+            const int nf = Sh::nf(ts, kt);
+            const int s = kt * kMaxFT;
+            if (nf == 1) {
+              if (Sh::prim(ts, kt, 0) == MU_STG) {
+                acc = fma(fma(-u[s], u[s], 1.0), s0[s], acc);
+              } else {
+                acc += s0[s];
+              }
+            } else {
+              double others = 1.0;
+#pragma unroll
+              for (int f = 1; f < kMaxFT; ++f) {
+                if (f < nf) {
+                  const int q = s + f;
+                  const double v = Sh::prim(ts, kt, f) == MU_STG ? fma(fma(-u[q], u[q], 1.0), s0[q], kThird) : s0[q];
+                  others = f == 1 ? v : others * v;
+                }
+              }
+              acc = fma(s0[s], others, acc);
+            }
+          }
+        }
+        const double N = acc;
+        if constexpr (MODE == kModeModel) {
+          S.model_out[idx] = N;
+        } else {
+          double dN;
+          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
+        }
+      } else if constexpr (MODE != kModeGrad) {
         double A = 0.0;
 #pragma unroll
         for (int kt = 0; kt < kMaxT; ++kt) {
@@ -599,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
         }
         const double N = fma(n0 * E, 1.0 + A, nbkg);
         if constexpr (MODE == kModeModel) {
-          J.model_out[idx] = N;
+          S.model_out[idx] = N;
         } else {
           double dN;
           lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
@@ -660,25 +808,63 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) {
         const int kt = s / kMaxFT, f = s % kMaxFT;
-        if (kt < n_terms && f < Sh::nf(ts, kt)) advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+        if (kt < n_terms && f < Sh::nf(ts, kt)) {
+          advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+          if (kScaled && Sh::prim(ts, kt, f) == MU_STG) u[s] += su[s];
+        }
       }
-    t += h;
+    if constexpr (!kScaled) t += h;
   };
 
   for (int k0 = 0; k0 < n_max; k0 += every) {
     // exact re-evaluation (anchor) at the first step of the segment
     t = fma((double)k0, h, t_first);
-    E = x_exp(neg_inv_tau * t);
+    const double life = x_exp(neg_inv_tau * t);
+    E = kScaled ? ecoef * life : life;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
       const int kt = s / kMaxFT, f = s % kMaxFT;
-      if (kt < n_terms && f < Sh::nf(ts, kt))
-        anchor(Sh::prim(ts, kt, f), t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
+      if (kt < n_terms && f < Sh::nf(ts, kt)) {
+        const int p = Sh::prim(ts, kt, f);
+        anchor(p, t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
+        if constexpr (kScaled) {
+          if (p == MU_STG) {
+            u[s] = R[kArg0 + 2 * s] * t;
+            s0[s] *= kTwoThird;
+          }
+          if (f == 0) {
+            const double L = (n0 * (coef[kt] * R[2 + kt])) * life;
+            s0[s] *= L;
+            if (p == MU_TF) s1[s] *= L;
+            if (p == MU_SG || p == MU_STG) s1[s] *= rE;  // q: the Gaussian step also carries the lifetime
+          }
+        }
+      }
     }
     const int k1 = min(n_full, k0 + every);
-#pragma unroll 2
-    for (int k = k0; k < k1; ++k) bin_step(k);  // uniform trip count
-    if (extra && k1 == n_full && n_full < k0 + every) bin_step(n_full);
+    int k = k0;
+    // reads of steps k + kPrefetch .. k + 2 kPrefetch - 1 from one pointer
+    GlobalCT nxt = cp + (int64_t)(k0 + kPrefetch) * kBlock;
+    for (; k + kPrefetch <= k1; k += kPrefetch, nxt += kPrefetch * kBlock) {  // uniform trip count
+#pragma unroll
+      for (int i = 0; i < kPrefetch; ++i) {
+        const double d = (double)dq[i];  // widened first: the load can reuse its register
+        if constexpr (MODE != kModeModel) {
+          dq[i] = nxt[i * kBlock];
+          // keep the read here, a full kPrefetch steps before its use (the
+          // scheduler would otherwise sink it towards the end of the loop)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        bin_step(k + i, d);
+      }
+    }
+    // only the last segment has a tail: under kPrefetch uniform steps, then
+    // this lane's ragged extra step
+    if (k < k0 + every) {
+#pragma unroll
+      for (int i = 0; i < kPrefetch; ++i)
+        if (k + i < n_full || (extra && k + i == n_full)) bin_step(k + i, (double)dq[i]);
+    }
   }
   if constexpr (MODE == kModeModel) return;
 
@@ -706,8 +892,6 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
     }
   }
   __syncthreads();
-  // the job's slots are global across the per-shape launches of one batch
-  double *slot = a.partial + ((int64_t)J.tile_base + (b - J.block_base)) * kSlot;
   if (tid == 0) {
     Pair t = wred[0];
     for (int q = 1; q < kBlock / 64; ++q) t = pair_add(t, wred[q]);
@@ -720,6 +904,99 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(LaunchArgs a) {
       for (int q = 1; q < kBlock / 64; ++q) s += gred[q][tid];
       slot[2 + tid] = s;
     }
+  }
+}
+
+// Index of the histogram whose fit range holds offset `off` of a vector's
+// concatenated fit ranges (offsets are prefix sums, first 0).
+__device__ __forceinline__ int histo_at(const DevHisto *hs, int n_histo, int64_t off) {
+  int lo = 0, hi = n_histo - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (hs[mid].off <= off) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Tile launch: workgroup b evaluates tile b of its job.
+// Split launch (uniform jobs, split_w > 0): the n_vec x total (vector, bin)
+// space is cut into equal ranges of split_w bins, one per workgroup, so every
+// workgroup has the same work; a range is evaluated as the (vector, histogram)
+// segments it crosses. Segment (workgroup b, histogram j = v * n_histo + h)
+// owns slot b + j: the sum grows by one or two from one segment to the next,
+// so slots are unique and each histogram's slots are contiguous. When a range
+// starts exactly at a histogram start, slot b + j - 1 belongs to no segment
+// and is written as zero so that every slot inside a vector's span is defined.
+// Minimum waves per SIMD asked of the register allocator: the chi^2 cost
+// kernels of the compiled shapes fit six (80 registers) without spilling;
+// the others are left to the compiler's own choice.
+template <int COST, int MODE, typename Sh>
+constexpr int eval_min_waves() {
+  return (COST == MU_COST_CHI2 && MODE == kModeCost && Sh::kFixed) ? 6 : 1;
+}
+
+template <int COST, int MODE, typename CT, typename Sh>
+__global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
+  const int b = blockIdx.x;
+  const bool split = a.split_w != 0;
+  const int nh = a.tmpl.n_histo;
+  int64_t pos = 0, end = 0;
+  int v = 0, h = 0;
+  if (split) {
+    pos = (int64_t)b * a.split_w;
+    end = min(pos + a.split_w, (int64_t)a.n_vec * a.total);
+    if (pos >= end) return;
+    v = (int)(pos / a.total);
+    h = histo_at(a.tmpl.histos, nh, pos - (int64_t)v * a.total);
+    if (MODE != kModeModel && pos == (int64_t)v * a.total + a.tmpl.histos[h].off && (v > 0 || h > 0)) {
+      if (threadIdx.x < kSlot) a.partial[((int64_t)b + (int64_t)v * nh + h - 1) * kSlot + threadIdx.x] = 0.0;
+    }
+  }
+  for (;;) {
+    SegIn S;
+    DevHisto H;
+    double *slot;
+    int64_t seg_end = 0;
+    if (!split) {
+      int job;
+      const DevJob J = job_of(a, b, job);
+      const DevTile T = J.tiles[b - J.block_base];
+      H = J.histos[T.histo];
+      S.th = J.th;
+      S.p = J.p;
+      S.counts = J.counts;
+      S.model_out = J.model_out;
+      S.begin = T.begin;
+      S.n = T.n;
+      // the job's slots are global across the per-shape launches of one batch
+      slot = a.partial + ((int64_t)J.tile_base + (b - J.block_base)) * kSlot;
+    } else {
+      H = uni(a.tmpl.histos[h]);
+      const int64_t h_start = (int64_t)v * a.total + H.off;
+      seg_end = min(end, h_start + H.n);
+      S.th = a.tmpl.th;
+      S.p = a.tmpl.p + (int64_t)v * a.p_stride;
+      S.counts = a.tmpl.counts;
+      S.model_out = a.tmpl.model_out;
+      S.begin = pos - h_start;
+      S.n = (int32_t)(seg_end - pos);
+      slot = a.partial + ((int64_t)b + (int64_t)v * nh + h) * kSlot;
+    }
+    S.off = H.off;
+    S.first = H.first;
+    S.t0_bin = H.t0_bin;
+    S.dt = H.dt;
+    S.map_row = H.map_row;
+    S.anchor_every = a.anchor_every;
+    eval_segment<COST, MODE, CT, Sh>(S, slot);
+    if (!split) return;
+    pos = seg_end;
+    if (pos >= end) return;
+    if (++h == nh) {
+      h = 0;
+      ++v;
+    }
+    __syncthreads();  // the next segment reuses the reduction buffers
   }
 }
 
@@ -740,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(LaunchArgs a) {
   } else {
     J = a.jobs[job];
   }
-  merge_job<MODE>(a, J);
+  merge_job<MODE>(a, J, job);
 }
 
 template <int COST, int MODE, typename Sh>

@@ -16,6 +16,9 @@ constexpr int kMaxFT = MU_MAX_FACTORS_PER_TERM;
 // term k at kArg0 + (k * kMaxFT + i) * 2 + a.
 constexpr int kArg0 = 2 + kMaxT;
 constexpr int kRS = kArg0 + kMaxT * kMaxFT * 2;  // 30
+// Lane steps between a count's load and its use; the counts buffer is padded
+// by this many steps of 256 values.
+constexpr int kPrefetch = 4;
 // Partial slot of one tile: cost (s, c) then kRS gradient components.
 constexpr int kSlot = 2 + kRS;  // 32 doubles
 constexpr int kBlock = 256;     // threads per evaluation workgroup
@@ -99,9 +102,15 @@ struct LaunchArgs {
   const int32_t *block_job;
   int32_t n_blocks;
   int32_t cost_kind;
-  int32_t anchor_every;  // lane steps between exact re-evaluations, 1..64
-  int32_t pad0;
-  double *partial;    // [total tiles of all jobs][kSlot]
+  int32_t anchor_every;  // lane steps between exact re-evaluations, 1..256
+  // Split launch (jobs == null, split_w > 0): n_vec vectors of `total`
+  // fit-range bins each, cut into ranges of split_w bins, one per workgroup;
+  // slot b + v * n_histo + h of `partial` belongs to workgroup b's segment of
+  // histogram h of vector v.
+  int32_t n_vec;
+  int64_t split_w;
+  int64_t total;
+  double *partial;    // tile launch: [total tiles of all jobs][kSlot]
 };
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);

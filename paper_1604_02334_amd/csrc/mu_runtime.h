@@ -14,6 +14,7 @@ struct mu_ctx;
 namespace mu {
 
 constexpr int kMinTile = 1024, kMaxTile = 65536;
+constexpr int kMaxSplit = 1 << 26;  // largest explicit bins-per-workgroup value
 constexpr int kDefaultAnchor = 64;
 
 // Grow-only device buffer owned by a context.
@@ -61,12 +62,25 @@ struct mu_ctx {
   };
   std::vector<Tuned> tuned;
   int pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const;
+  // Bins per workgroup of a split launch (single dataset, n_vec vectors).
+  int64_t pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const;
   int specialize = 1;  // use the compiled shape kernels when a theory matches one
   hipEvent_t staging_free = nullptr;  // recorded after each upload from `staging`
   mu::DevBuf partial, dparams, dout, djobs;
   mu::HostBuf staging, staging_out;
   std::vector<mu::DevBuf> extra;
   void release_all();
+  // Launch timing (events on `stream` around kernel launches while enabled).
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;  // created on demand, destroyed with the context
+  struct Timed {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  // Records the start event of a timed launch; returns the index to close, or -1.
+  int time_begin(int kind);
+  void time_end(int idx);
   // Wait until the last upload from `staging` has been consumed.
   void wait_staging() {
     if (staging_free) hipEventSynchronize(staging_free);
@@ -96,6 +110,7 @@ struct mu_data {
   int64_t longest = 0;     // bins of the longest fit range
   std::vector<mu::DevHisto> hh;
   std::deque<mu::TileSet> sets;  // one per tile size used so far (few); stable addresses
+  mu::DevHisto *d_hh = nullptr;  // device copy of hh (split launches)
   // Tables for `tile_bins`, built on first use and kept until destruction.
   mu_status tiles(int tile_bins, const mu::TileSet **out);
   void free_dev();

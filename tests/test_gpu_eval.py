@@ -127,7 +127,9 @@ def test_c3_vectors_sampled(ctx):
     P = cfg["P"]
     got = api.chi2_eval(ctx, d, th, P)
     cg, gg = api.chi2_grad(ctx, d, th, P)
-    np.testing.assert_array_equal(cg, got)
+    # the cost pass folds N0, the lifetime and the term weights into its
+    # recurrence states, the gradient pass keeps them apart: equal to rounding
+    assert np.all(np.abs(cg - got) <= 1e-14 * np.abs(got))
     idx = np.random.default_rng(0).choice(P.shape[0], 48, replace=False)
     for v in idx:
         ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v])
@@ -264,7 +266,7 @@ def test_batch_uneven_datasets(ctx):
     for kind in ("chi2", "poisson"):
         c, g = api.chi2_batch(ctx, ds, ths, P, kind, grad=True)
         c_only = api.chi2_batch(ctx, ds, ths, P, kind)
-        np.testing.assert_array_equal(c, c_only)
+        assert np.all(np.abs(c - c_only) <= 1e-14 * np.abs(c_only))
         for j, s in enumerate(sets):
             n = s["start"].size
             ref = model.cost(s["theory"], s["histos"], cnts[j], s["start"], kind)
@@ -295,8 +297,8 @@ def test_torch_device_path_and_autograd(ctx):
 
 def test_specialised_kernels_match_generic_and_direct(ctx):
     """Each compiled shape against the generic interpreted kernel, and the
-    recurrence path (anchor every 64 steps) against direct evaluation of every
-    bin (anchor every step)."""
+    recurrence path (anchor every 64 steps) against the shortest anchor
+    interval (every fourth step) and the longest (256)."""
     _say("shapes vs generic, anchors")
     rng = np.random.default_rng(21)
     hs = [{"n_bins": 20000, "dt": 0.0005, "t0_bin": 0.0, "first": 3, "last": 19990, "map_row": 0}]
@@ -339,8 +341,34 @@ def test_autotune_choice_keeps_parity(ctx):
     th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
     P = np.stack([perturbed(cfg["p_true"], 1e-3, 30 + v) for v in range(64)])
     tile, anchor, us = api.autotune(ctx, d, th, P)
-    assert tile % 256 == 0 and 1024 <= tile <= 65536 and anchor in (32, 64, 128, 256) and us > 0
+    # bins per workgroup: a power of two or a whole-round split, at least one bin per lane
+    assert tile >= 256 and anchor in (32, 64, 128, 256) and us > 0
     got = api.chi2_eval(ctx, d, th, P)
     for v in (0, 17, 63):
         ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v])
         assert abs(got[v] - ref) <= REL * ref
+
+
+def test_kernel_timing_records_each_launch(ctx):
+    """Event timing counts every evaluation and merge launch by kind and gives
+    positive durations; disabling stops recording; enabling clears."""
+    _say("kernel timing")
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    P = np.stack([perturbed(cfg["p_true"], 1e-3, 40 + v) for v in range(4)])
+    ctx.timing(True)
+    api.chi2_eval(ctx, d, th, P)
+    api.chi2_eval(ctx, d, th, P[:1])
+    api.chi2_grad(ctx, d, th, P[:2])
+    ctx.timing(False)
+    api.chi2_eval(ctx, d, th, P)
+    n, ms = ctx.timing_read("cost")
+    assert n == 2 and ms > 0
+    n, ms = ctx.timing_read("grad")
+    assert n == 1 and ms > 0
+    n, ms = ctx.timing_read("merge")
+    assert n == 3 and ms > 0
+    assert ctx.timing_read("model") == (0, 0.0)
+    ctx.timing(True)
+    assert ctx.timing_read("cost") == (0, 0.0)
+    ctx.timing(False)

@@ -325,7 +325,7 @@ static mu_status check_histos(const mu_histo *h, int32_t n, std::string &why, bo
         why = b;
         return MU_E_ARG;
       }
-      if (ints && (d != std::floor(d) || d >= 16777216.0)) ints = false;
+      if (ints && (d != std::floor(d) || d >= 4294967296.0)) ints = false;
     }
   }
   if (all_int) *all_int = ints;
@@ -466,7 +466,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
     total += x.n;
   }
   d->total = total;
-  const size_t esz = d->f64 ? sizeof(double) : sizeof(float);
+  const size_t esz = d->f64 ? sizeof(double) : sizeof(uint32_t);
   // kPrefetch lane steps (of 256 values) of zero padding: kernels read each
   // lane's counts that many steps ahead, and reads past the last bin land here
   const size_t padded = ((size_t)total + (size_t)kPrefetch * kBlock) * esz;
@@ -486,7 +486,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
         if (d->f64)
           reinterpret_cast<double *>(buf.data())[x.off + i] = v;
         else
-          reinterpret_cast<float *>(buf.data())[x.off + i] = (float)v;
+          reinterpret_cast<uint32_t *>(buf.data())[x.off + i] = (uint32_t)v;
       }
     }
     e = hipMemcpy(d->counts, buf.data(), buf.size(), hipMemcpyHostToDevice);

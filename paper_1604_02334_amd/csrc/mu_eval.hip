@@ -318,14 +318,33 @@ __device__ __forceinline__ double value_grad(int kind, double t, double a0, doub
 }
 
 // Per-bin cost term (Eq. 2 / Eq. 3) and its derivative in N.
+// 1/v for v >= 1: hardware reciprocal refined by one Newton step (< 1 ulp +
+// rounding).
+__device__ __forceinline__ double recip(double v) {
+  double iv = __builtin_amdgcn_rcp(v);
+  return fma(iv, fma(-v, iv, 1.0), iv);
+}
+
+// 1 / max(d, 1) of an integer count: from the workgroup's table (correctly
+// rounded) below kInvTab, else by recip().
+__device__ __forceinline__ double inv_count(uint32_t raw, double d, const double *tab) {
+  double iv = tab[min(raw, (uint32_t)(kInvTab - 1))];
+  // a wave-uniform test, so the rare large counts cost a skipped scalar branch
+  if (__builtin_amdgcn_ballot_w64(raw >= (uint32_t)kInvTab) != 0) {
+    asm volatile("");  // keeps the branch: not speculated into every bin
+    if (raw >= (uint32_t)kInvTab) iv = recip(d);
+  }
+  return iv;
+}
+
+// Per-bin cost term (Eq. 2 / Eq. 3) and its derivative in N. For chi^2 on
+// integer counts the caller passes iv = 1 / max(d, 1); otherwise it is
+// computed here.
 template <int COST, bool WANT_DN, bool INT_DATA>
-__device__ __forceinline__ double cost_term(double d, double N, double &dN) {
+__device__ __forceinline__ double cost_term(double d, double N, double iv_int, double &dN) {
   if (COST == MU_COST_CHI2) {
-    // variance d, or 1 for an empty bin; integer counts: max(d, 1) is the same
-    const double v = INT_DATA ? fmax(d, 1.0) : (d > 0.0 ? d : 1.0);
-    // 1/v: hardware reciprocal refined by one Newton step (< 1 ulp + rounding)
-    double iv = __builtin_amdgcn_rcp(v);
-    iv = fma(iv, fma(-v, iv, 1.0), iv);
+    // variance d, or 1 for an empty bin
+    const double iv = INT_DATA ? iv_int : recip(d > 0.0 ? d : 1.0);
     const double diff = d - N;
     if (WANT_DN) dN = -2.0 * diff * iv;
     return diff * diff * iv;
@@ -556,6 +575,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
 // concatenated counts), evaluated for the parameter vector p; the workgroup's
 // cost (and gradient) partials go to its slot.
 struct SegIn {
+  const double *inv_tab;  // chi^2 on integer counts: 1 / max(d, 1) for d < kInvTab (LDS)
   const DevTheory *th;
   const double *p;
   const void *counts;
@@ -695,7 +715,13 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   double t = t_first;
 
   // one bin: value, cost term (or model value), gradient, then advance
-  auto bin_step = [&](int k, double d_cur) {
+  // chi^2 on integer counts reads 1 / max(d, 1) from the workgroup's table
+  constexpr bool kTable = COST == MU_COST_CHI2 && kIntData && MODE != kModeModel;
+  auto inv_of = [&](CT raw, double d) -> double {
+    if constexpr (kTable) return inv_count((uint32_t)raw, d, S.inv_tab);
+    return 0.0;
+  };
+  auto bin_step = [&](int k, double d_cur, double iv) {
     const int64_t idx = idx0 + (int64_t)k * kBlock;
       if constexpr (kScaled) {
         double acc = E + nbkg;
@@ -729,7 +755,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
           S.model_out[idx] = N;
         } else {
           double dN;
-          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
+          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, iv, dN);
         }
       } else if constexpr (MODE != kModeGrad) {
         double A = 0.0;
@@ -750,7 +776,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
           S.model_out[idx] = N;
         } else {
           double dN;
-          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, dN);
+          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, iv, dN);
         }
       } else {
         double val[kSlots], d0[kSlots], d1[kSlots];
@@ -776,7 +802,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         }
         const double N = fma(n0 * E, 1.0 + A, nbkg);
         double dN;
-        lane_cost += cost_term<COST, true, kIntData>(d_cur, N, dN);
+        lane_cost += cost_term<COST, true, kIntData>(d_cur, N, iv, dN);
         const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
         const double rNE = rE * n0;  // r N0 e^(-t/tau)
         g[0] = fma(rE, 1.0 + A, g[0]);
@@ -848,14 +874,15 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     for (; k + kPrefetch <= k1; k += kPrefetch, nxt += kPrefetch * kBlock) {  // uniform trip count
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i) {
-        const double d = (double)dq[i];  // widened first: the load can reuse its register
+        const double d = (double)dq[i];  // widened (and looked up) first: the load can reuse its register
+        const double iv = inv_of(dq[i], d);
         if constexpr (MODE != kModeModel) {
           dq[i] = nxt[i * kBlock];
           // keep the read here, a full kPrefetch steps before its use (the
           // scheduler would otherwise sink it towards the end of the loop)
           __builtin_amdgcn_sched_barrier(0);
         }
-        bin_step(k + i, d);
+        bin_step(k + i, d, iv);
       }
     }
     // only the last segment has a tail: under kPrefetch uniform steps, then
@@ -863,7 +890,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     if (k < k0 + every) {
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i)
-        if (k + i < n_full || (extra && k + i == n_full)) bin_step(k + i, (double)dq[i]);
+        if (k + i < n_full || (extra && k + i == n_full)) bin_step(k + i, (double)dq[i], inv_of(dq[i], (double)dq[i]));
     }
   }
   if constexpr (MODE == kModeModel) return;
@@ -938,6 +965,12 @@ constexpr int eval_min_waves() {
 template <int COST, int MODE, typename CT, typename Sh>
 __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
   const int b = blockIdx.x;
+  constexpr bool kTable = COST == MU_COST_CHI2 && sizeof(CT) == 4 && MODE != kModeModel;
+  __shared__ double inv_tab[kTable ? kInvTab : 1];
+  if constexpr (kTable) {
+    for (int i = threadIdx.x; i < kInvTab; i += kBlock) inv_tab[i] = 1.0 / (double)(i > 0 ? i : 1);
+    __syncthreads();
+  }
   const bool split = a.split_w != 0;
   const int nh = a.tmpl.n_histo;
   int64_t pos = 0, end = 0;
@@ -988,6 +1021,7 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
     S.dt = H.dt;
     S.map_row = H.map_row;
     S.anchor_every = a.anchor_every;
+    S.inv_tab = inv_tab;
     eval_segment<COST, MODE, CT, Sh>(S, slot);
     if (!split) return;
     pos = seg_end;
@@ -1026,7 +1060,7 @@ hipError_t launch_shape(const LaunchArgs &a, int count_f64, hipStream_t s) {
   if (count_f64)
     hipLaunchKernelGGL((eval_kernel<COST, MODE, double, ShapeGeneric>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((eval_kernel<COST, MODE, float, Sh>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, Sh>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1039,7 +1073,7 @@ int occupancy_shape(int count_f64) {
         &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, double, ShapeGeneric>), kBlock, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, float, Sh>), kBlock, 0);
+        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, Sh>), kBlock, 0);
   return e == hipSuccess ? nb : 0;
 }
 

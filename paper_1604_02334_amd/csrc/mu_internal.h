@@ -19,6 +19,9 @@ constexpr int kRS = kArg0 + kMaxT * kMaxFT * 2;  // 30
 // Lane steps between a count's load and its use; the counts buffer is padded
 // by this many steps of 256 values.
 constexpr int kPrefetch = 4;
+// Entries of the per-workgroup table of 1 / max(d, 1) for integer counts
+// d < kInvTab (chi^2 kernels; FP64, 16 KiB of LDS).
+constexpr int kInvTab = 2048;
 // Partial slot of one tile: cost (s, c) then kRS gradient components.
 constexpr int kSlot = 2 + kRS;  // 32 doubles
 constexpr int kBlock = 256;     // threads per evaluation workgroup

@@ -168,12 +168,15 @@ __global__ __launch_bounds__(256) void gen_kernel(unsigned long long seed, unsig
 // (two equations m = N0 e + Nbkg, e the lifetime decay averaged over the
 // window) and ebar_b the decay averaged over rebinned bin b.  m1 and m2 are
 // also written for the default start.
-__global__ __launch_bounds__(256) void prep_kernel(const float *const *src, const float *contig, int rebin, int n,
+// Inputs either from datasets (src: one uint32 count array per sample) or from
+// the generator's contiguous FP32 counts (contig).
+__global__ __launch_bounds__(256) void prep_kernel(const uint32_t *const *src, const float *contig, int rebin, int n,
                                                    unsigned short *X, double *n0_out, double *m_first,
                                                    double *m_last) {
   const int s = blockIdx.x;
   if (s >= n) return;
-  const float *p = src ? src[s] : contig + (size_t)s * kCoarse * rebin;
+  const uint32_t *pu = src ? src[s] : nullptr;
+  const float *pf = src ? nullptr : contig + (size_t)s * kCoarse * rebin;
   constexpr int kWin = 32;  // rebinned bins per estimation window
   __shared__ double red[256];
   __shared__ double red2[256];
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *const *src, cons
   for (int q = 0; q < kCoarse / 256; ++q) {
     const int b = threadIdx.x + q * 256;
     double v = 0.0;
-    for (int r = 0; r < rebin; ++r) v += (double)p[b * rebin + r];
+    for (int r = 0; r < rebin; ++r) v += pu ? (double)pu[b * rebin + r] : (double)pf[b * rebin + r];
     c[q] = v;
     if (b < kWin) w1 += v;
     if (b >= kCoarse - kWin) w2 += v;
@@ -808,7 +811,7 @@ extern "C" mu_status mu_seeder_train(mu_ctx *ctx, mu_seeder *S, const mu_seed_tr
     const unsigned long long first = (unsigned long long)o->first_sample + (unsigned long long)k * B;
     hipLaunchKernelGGL(gen_kernel, dim3(B), dim3(256), 0, ctx->stream, (unsigned long long)o->seed, first, B, 0,
                        S->counts, S->theta, S->T, (double *)nullptr);
-    hipLaunchKernelGGL(prep_kernel, dim3(B), dim3(256), 0, ctx->stream, (const float *const *)nullptr, S->counts, 1,
+    hipLaunchKernelGGL(prep_kernel, dim3(B), dim3(256), 0, ctx->stream, (const uint32_t *const *)nullptr, S->counts, 1,
                        B, S->X[0], S->scale, (double *)nullptr, (double *)nullptr);
     // cosine decay from lr to lr * lr_final_frac
     const double frac = o->steps > 1 ? (double)k / (o->steps - 1) : 0.0;
@@ -832,7 +835,7 @@ extern "C" mu_status mu_seed_infer(mu_ctx *ctx, const mu_seeder *Sc, int32_t n, 
     if (ctx) set_err(ctx, "mu_seed_infer needs a seeder, n >= 1, data, start_out and ok_out");
     return MU_E_ARG;
   }
-  std::vector<const float *> src(n);
+  std::vector<const uint32_t *> src(n);
   for (int i = 0; i < n; ++i) {
     const mu_data *d = data[i];
     if (!d || d->ctx != ctx || d->n_histo != 1 || d->f64 || d->total != kFine || d->hh[0].first != 0 ||
@@ -841,14 +844,15 @@ extern "C" mu_status mu_seed_infer(mu_ctx *ctx, const mu_seeder *Sc, int32_t n, 
               i);
       return MU_E_ARG;
     }
-    src[i] = static_cast<const float *>(d->counts);
+    src[i] = static_cast<const uint32_t *>(d->counts);
   }
   hipSetDevice(ctx->device);
   mu_status st = S->ensure(n);
   if (st != MU_OK) return st;
   hipError_t e = hipMemcpyAsync(S->srcs, src.data(), n * sizeof(void *), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(prep_kernel, dim3(n), dim3(256), 0, ctx->stream, S->srcs, (const float *)nullptr, kRebin, n,
+    hipLaunchKernelGGL(prep_kernel, dim3(n), dim3(256), 0, ctx->stream, (const uint32_t *const *)S->srcs,
+                       (const float *)nullptr, kRebin, n,
                        S->X[0], S->scale, S->mf, S->ml);
     e = hipGetLastError();
   }

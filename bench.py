@@ -33,20 +33,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 vector
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 vector (FMA = 2 flops)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
-# Algorithmic FP64 flops per bin of the cost pass on this theory with the
-# recurrence formulation (FMA = 2 flops): lifetime step 1, exponential step 1,
-# rotation 6, product 1, first term 2, Kubo-Toyabe (two Gaussian steps, time,
-# polynomial) 10, second term 2, histogram model 4, chi^2 term with the
-# refined reciprocal 8, accumulation 1.
-FLOPS_PER_BIN_CHI2 = 36
-# The same count with every FP64 instruction as one operation (FMA = 1), and
-# the FP64 vector issue rate it is set against: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz = 39.3 T lane-operations per second.
-OPS_PER_BIN_CHI2 = 26
+# FP64 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T
+# lane-operations per second (one instruction per lane, FMA counted once).
 PEAK_FP64_TOPS = 39.3
-BYTES_PER_BIN = 4         # one FP32 count streamed per bin evaluation
+# Per bin of the 16-detector cost pass as the kernel computes it (lifetime,
+# N0 and term weights folded into the first factor of each term; reciprocal
+# variance from the workgroup's table):
+#   model: lifetime 1 mul, exponential 1 mul, rotation 2 mul + 2 fma, Gaussian
+#   2 mul, sigma t 1 add, 1 - (sigma t)^2 1 fma, background 1 add, two term
+#   accumulations 2 fma                       -> 13 instructions, 18 flops
+#   chi^2: d - N, square, times 1/v, accumulate ->  4 instructions,  4 flops
+#   plus widening d, clamping and scaling the table index, range test
+#                                               ->  4 instructions,  0 flops
+FLOPS_PER_BIN_CHI2 = 22   # FMA = 2
+VALU_PER_BIN_CHI2 = 21    # instructions per bin of the per-bin loop
+BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
+COUNTERS = os.path.join(ROOT, "profiles", "eval_kernel_c2_stencil_counters.md")
+KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h"]
+
+
+def _kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counters():
+    """Hardware-counter figures of the stencil launch from the committed
+    summary, if it was taken on the current kernel sources (else None)."""
+    import re
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel sources sha256\[:16\]: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != _kernel_hash():
+        return None
+    out = {}
+    for key in ("hbm_bytes_per_launch", "valu_instr_per_bin"):
+        mm = re.search(key + r": `([0-9.e+]+)`", text)
+        if mm:
+            out[key] = float(mm.group(1))
+    return out
 
 
 def _log(*a):
@@ -348,7 +381,9 @@ def main():
     value = bins_per_step / (wall / args.steps) / 1e9
     k_ms = ms_cost / n_cost
     k_bins = stencil.shape[0] * n_bins
-    achieved = FLOPS_PER_BIN_CHI2 * k_bins / (k_ms * 1e-3) / 1e12
+    rate = k_bins / (k_ms * 1e-3)  # bins per second in the stencil kernel
+    achieved = FLOPS_PER_BIN_CHI2 * rate / 1e12
+    ctr = _counters()
     out = {
         "metric": "chi2 Gbin/s (FP64 acc, 1e-10 rel)",
         "value": round(value, 3),
@@ -366,11 +401,22 @@ def main():
                    "histograms": 16, "bins_per_histogram": 65536, "params": 52,
                    "vectors_per_step": 1 + stencil.shape[0], "bins_per_step": bins_per_step},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                     "kernel": "eval_kernel<chi2, cost, float>", "kernel_ms": round(k_ms, 5),
-                     "flops_per_bin": FLOPS_PER_BIN_CHI2, "bins_per_launch": k_bins},
-        "extra": {"stencil_kernel_gbin_s": round(k_bins / (k_ms * 1e-3) / 1e9, 2),
-                  "fp64_op_issue_frac": round(OPS_PER_BIN_CHI2 * k_bins / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TOPS, 4),
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "traffic": ctr.get("hbm_bytes_per_launch") if ctr else None,
+                     "kernel": "eval_kernel<chi2, cost, uint32, exp*cos + stg>", "kernel_ms": round(k_ms, 5),
+                     "flops_per_bin": FLOPS_PER_BIN_CHI2, "bins_per_launch": k_bins,
+                     "algorithmic_bytes_per_launch": BYTES_PER_BIN * k_bins,
+                     # the binding limit of this instruction mix: VALU issue
+                     "valu_issue": {
+                         "instr_per_bin": VALU_PER_BIN_CHI2,
+                         "frac": round(VALU_PER_BIN_CHI2 * rate / 1e12 / PEAK_FP64_TOPS, 4),
+                         "measured_instr_per_bin": ctr.get("valu_instr_per_bin") if ctr else None,
+                         "measured_frac": (round(ctr["valu_instr_per_bin"] * rate / 1e12 / PEAK_FP64_TOPS, 4)
+                                           if ctr and "valu_instr_per_bin" in ctr else None),
+                         "peak_tops": PEAK_FP64_TOPS,
+                         "attainable_flop_frac": round(FLOPS_PER_BIN_CHI2 / VALU_PER_BIN_CHI2 * PEAK_FP64_TOPS
+                                                       / PEAK_FP64_TFLOPS, 4)}},
+        "extra": {"stencil_kernel_gbin_s": round(rate / 1e9, 2),
                   "tuned_stencil": {"tile": tune_eval[0], "anchor": tune_eval[1]},
                   "tuned_grad": {"tile": tune_grad[0], "anchor": tune_grad[1]},
                   "grad_kernel_us": round(ms_grad / n_grad * 1e3, 2),

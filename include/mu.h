@@ -188,6 +188,18 @@ mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu
                        const double *params, int32_t n_vec, unsigned mem,
                        double *cost, double *grad);
 
+/* A minimiser's step over one dataset in one call: cost and gradient at the
+ * n_grad vectors params_grad ([n_grad][n_par]) as mu_chi2_grad, and the cost
+ * at the n_cost vectors params_cost ([n_cost][n_par]) as mu_chi2_eval (trial
+ * or finite-difference points; Sec. 4 and Table 1 count such evaluations).
+ * Both passes run on the context's stream and share one merge launch.
+ * Results are bitwise those of the two separate calls.  Outputs:
+ * cost_grad [n_grad], grad [n_grad][n_par], cost [n_cost].  mem applies to
+ * all parameter and output arrays.  Errors as mu_chi2_eval. */
+mu_status mu_chi2_eval_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                            const double *params_grad, int32_t n_grad, const double *params_cost,
+                            int32_t n_cost, unsigned mem, double *cost_grad, double *grad, double *cost);
+
 /* Batched evaluation of n_jobs independent (dataset, theory, parameter
  * vector) jobs of uneven sizes in one launch.  params: [n_jobs][ld] with
  * ld >= every theory's n_par (each job reads its first n_par entries).

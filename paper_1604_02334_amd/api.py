@@ -306,6 +306,40 @@ def chi2_grad(ctx, data, theory, params, cost="chi2"):
     return out, g
 
 
+def chi2_eval_grad(ctx, data, theory, params_grad, params_cost, cost="chi2"):
+    """Cost and gradient at params_grad and cost at params_cost in one call
+    (the two passes overlap on the device). Returns (cost_grad, grad, cost)."""
+    L = A.lib()
+    if _is_torch(params_grad) and params_grad.is_cuda:
+        import torch
+        pg = params_grad.detach().to(torch.float64).contiguous()
+        pc = params_cost.detach().to(torch.float64).contiguous()
+        if pg.dim() == 1:
+            pg = pg[None]
+        if pc.dim() == 1:
+            pc = pc[None]
+        dev = pg.device
+        cg = torch.empty(pg.shape[0], dtype=torch.float64, device=dev)
+        g = torch.empty((pg.shape[0], theory.n_par), dtype=torch.float64, device=dev)
+        cc = torch.empty(pc.shape[0], dtype=torch.float64, device=dev)
+        cur = ctx._enter_device()
+        _check(L.mu_chi2_eval_grad(ctx.h, data.h, theory.h, _cost_code(cost), C.c_void_p(pg.data_ptr()), pg.shape[0],
+                                   C.c_void_p(pc.data_ptr()), pc.shape[0], A.MU_MEM_DEVICE,
+                                   C.c_void_p(cg.data_ptr()), C.c_void_p(g.data_ptr()), C.c_void_p(cc.data_ptr())),
+               ctx.h, "mu_chi2_eval_grad")
+        ctx._leave_device(cur, [pg, pc, cg, g, cc])
+        return cg, g, cc
+    pg = _as_host_params(params_grad, theory.n_par)
+    pc = _as_host_params(params_cost, theory.n_par)
+    cg = np.empty(pg.shape[0])
+    g = np.empty((pg.shape[0], theory.n_par))
+    cc = np.empty(pc.shape[0])
+    _check(L.mu_chi2_eval_grad(ctx.h, data.h, theory.h, _cost_code(cost), pg.ctypes.data, pg.shape[0], pc.ctypes.data,
+                               pc.shape[0], A.MU_MEM_HOST, cg.ctypes.data, g.ctypes.data, cc.ctypes.data),
+           ctx.h, "mu_chi2_eval_grad")
+    return cg, g, cc
+
+
 def chi2_batch(ctx, datas, theories, params, cost="chi2", grad=False):
     """One launch over independent (dataset, theory, vector) jobs.
     params: [n_jobs, ld] with ld >= every theory's n_par."""

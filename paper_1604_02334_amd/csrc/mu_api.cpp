@@ -176,6 +176,7 @@ extern "C" mu_status mu_ctx_destroy(mu_ctx *ctx) {
 
 void mu_ctx::release_all() {
   partial.release();
+  partial_aux.release();
   dparams.release();
   dout.release();
   djobs.release();
@@ -184,7 +185,7 @@ void mu_ctx::release_all() {
   for (auto &b : extra) b.release();
 }
 
-int mu_ctx::time_begin(int kind) {
+int mu_ctx::time_begin(int kind, hipStream_t s) {
   if (!timing) return -1;
   const size_t need = 2 * (timed.size() + 1);
   while (ev_pool.size() < need) {
@@ -194,13 +195,13 @@ int mu_ctx::time_begin(int kind) {
     ev_pool.push_back(ev);
   }
   Timed t{kind, ev_pool[need - 2], ev_pool[need - 1]};
-  if (hipEventRecord(t.a, stream) != hipSuccess) return -1;
+  if (hipEventRecord(t.a, s) != hipSuccess) return -1;
   timed.push_back(t);
   return (int)timed.size() - 1;
 }
 
-void mu_ctx::time_end(int idx) {
-  if (idx >= 0) hipEventRecord(timed[idx].b, stream);
+void mu_ctx::time_end(int idx, hipStream_t s) {
+  if (idx >= 0) hipEventRecord(timed[idx].b, s);
 }
 
 extern "C" mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable) {
@@ -799,9 +800,7 @@ mu_status check_pair(mu_ctx *ctx, const mu_data *d, const mu_theory *th) {
 namespace mu {
 
 // Evaluate n_vec vectors over one dataset in one launch.  mode: cost, grad, model.
-mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *params,
-                       int32_t n_vec, unsigned mem, double *cost, double *histo, double *grad, double *model,
-                       int mode) {
+static mu_status check_eval_args(mu_ctx *ctx, int cost_kind, unsigned mem, int32_t n_vec, const void *params) {
   if (mem != MU_MEM_HOST && mem != MU_MEM_DEVICE) {
     set_err(ctx, "mem must be MU_MEM_HOST or MU_MEM_DEVICE");
     return MU_E_ARG;
@@ -814,8 +813,19 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
     set_err(ctx, "need n_vec >= 1 and a parameter array");
     return MU_E_ARG;
   }
+  return MU_OK;
+}
+
+// A launched evaluation whose merge is still to be enqueued.
+struct Pending {
+  LaunchArgs a;
+  int mode = 0, n_vec = 0;
+};
+
+static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp,
+                             int32_t n_vec, double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s,
+                             DevBuf &partial, Pending &pend) {
   mu_status st;
-  hipSetDevice(ctx->device);
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
   int anchor = ctx->anchor_every;
   const int64_t work = (int64_t)n_vec * d->total;
@@ -826,35 +836,10 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
     set_err(ctx, "launch needs more than 2^31 workgroups");
     return MU_E_UNSUPPORTED;
   }
-  const size_t n_p = (size_t)n_vec * n_par;
-  const size_t n_h = histo ? (size_t)n_vec * d->n_histo : 0;
-  const size_t n_g = grad ? (size_t)n_vec * n_par : 0;
-  const size_t n_c = mode == kModeModel ? 0 : (size_t)n_vec;
-  const size_t n_m = mode == kModeModel ? (size_t)d->total : 0;
-  const double *dp = params;
-  double *dc = cost, *dh = histo, *dg = grad, *dm = model;
-  hipError_t e;
-  if (mem == MU_MEM_HOST) {
-    if ((st = ctx->dparams.ensure(ctx, n_p * sizeof(double), false)) != MU_OK) return st;
-    if ((st = ctx->dout.ensure(ctx, (n_c + n_h + n_g + n_m) * sizeof(double), false)) != MU_OK) return st;
-    if ((st = ctx->staging.ensure(ctx, n_p * sizeof(double))) != MU_OK) return st;
-    if ((st = ctx->staging_out.ensure(ctx, (n_c + n_h + n_g + n_m) * sizeof(double))) != MU_OK) return st;
-    ctx->wait_staging();
-    std::memcpy(ctx->staging.ptr, params, n_p * sizeof(double));
-    e = hipMemcpyAsync(ctx->dparams.ptr, ctx->staging.ptr, n_p * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(params)");
-    ctx->mark_staging();
-    dp = static_cast<double *>(ctx->dparams.ptr);
-    double *o = static_cast<double *>(ctx->dout.ptr);
-    dc = n_c ? o : nullptr;
-    dh = n_h ? o + n_c : nullptr;
-    dg = n_g ? o + n_c + n_h : nullptr;
-    dm = n_m ? o + n_c + n_h + n_g : nullptr;
-  }
   if (mode != kModeModel) {
     // slot b + v * n_histo + h for every segment (see the split launch)
     const size_t n_slots = (size_t)n_blocks + (size_t)n_vec * d->n_histo;
-    if ((st = ctx->partial.ensure(ctx, n_slots * kSlot * sizeof(double), false)) != MU_OK) return st;
+    if ((st = partial.ensure(ctx, n_slots * kSlot * sizeof(double), false)) != MU_OK) return st;
   }
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
@@ -880,19 +865,69 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
   a.n_vec = n_vec;
   a.split_w = W;
   a.total = d->total;
-  a.partial = static_cast<double *>(ctx->partial.ptr);
-  int ti = ctx->time_begin(mode == kModeGrad ? MU_TIME_EVAL_GRAD
+  a.partial = static_cast<double *>(partial.ptr);
+  int ti = ctx->time_begin(mode == kModeGrad    ? MU_TIME_EVAL_GRAD
                            : mode == kModeModel ? MU_TIME_EVAL_MODEL
-                                                : MU_TIME_EVAL_COST);
-  e = launch_eval(a, mode, d->f64, shape, ctx->stream);
-  ctx->time_end(ti);
+                                                : MU_TIME_EVAL_COST,
+                           s);
+  hipError_t e = launch_eval(a, mode, d->f64, shape, s);
+  ctx->time_end(ti, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
-  if (mode != kModeModel) {
-    ti = ctx->time_begin(MU_TIME_MERGE);
-    e = launch_merge(a, mode, n_vec, ctx->stream);
-    ctx->time_end(ti);
-    if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
+  pend.a = a;
+  pend.mode = mode;
+  pend.n_vec = n_vec;
+  return MU_OK;
+}
+
+static mu_status eval_merge(mu_ctx *ctx, const Pending &pend, hipStream_t s) {
+  if (pend.mode == kModeModel) return MU_OK;
+  const int ti = ctx->time_begin(MU_TIME_MERGE, s);
+  hipError_t e = launch_merge(pend.a, pend.mode, pend.n_vec, s);
+  ctx->time_end(ti, s);
+  return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "merge launch");
+}
+
+mu_status eval_dev(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp, int32_t n_vec,
+                   double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s, DevBuf &partial) {
+  Pending pend;
+  mu_status st = eval_launch(ctx, d, th, cost_kind, dp, n_vec, dc, dh, dg, dm, mode, s, partial, pend);
+  return st == MU_OK ? eval_merge(ctx, pend, s) : st;
+}
+
+mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *params,
+                       int32_t n_vec, unsigned mem, double *cost, double *histo, double *grad, double *model,
+                       int mode) {
+  mu_status st = check_eval_args(ctx, cost_kind, mem, n_vec, params);
+  if (st != MU_OK) return st;
+  hipSetDevice(ctx->device);
+  const int n_par = th->h.n_par;
+  const size_t n_p = (size_t)n_vec * n_par;
+  const size_t n_h = histo ? (size_t)n_vec * d->n_histo : 0;
+  const size_t n_g = grad ? (size_t)n_vec * n_par : 0;
+  const size_t n_c = mode == kModeModel ? 0 : (size_t)n_vec;
+  const size_t n_m = mode == kModeModel ? (size_t)d->total : 0;
+  const double *dp = params;
+  double *dc = cost, *dh = histo, *dg = grad, *dm = model;
+  hipError_t e;
+  if (mem == MU_MEM_HOST) {
+    if ((st = ctx->dparams.ensure(ctx, n_p * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->dout.ensure(ctx, (n_c + n_h + n_g + n_m) * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->staging.ensure(ctx, n_p * sizeof(double))) != MU_OK) return st;
+    if ((st = ctx->staging_out.ensure(ctx, (n_c + n_h + n_g + n_m) * sizeof(double))) != MU_OK) return st;
+    ctx->wait_staging();
+    std::memcpy(ctx->staging.ptr, params, n_p * sizeof(double));
+    e = hipMemcpyAsync(ctx->dparams.ptr, ctx->staging.ptr, n_p * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(params)");
+    ctx->mark_staging();
+    dp = static_cast<double *>(ctx->dparams.ptr);
+    double *o = static_cast<double *>(ctx->dout.ptr);
+    dc = n_c ? o : nullptr;
+    dh = n_h ? o + n_c : nullptr;
+    dg = n_g ? o + n_c + n_h : nullptr;
+    dm = n_m ? o + n_c + n_h + n_g : nullptr;
   }
+  if ((st = eval_dev(ctx, d, th, cost_kind, dp, n_vec, dc, dh, dg, dm, mode, ctx->stream, ctx->partial)) != MU_OK)
+    return st;
   if (mem == MU_MEM_HOST) {
     const size_t n_out = n_c + n_h + n_g + n_m;
     e = hipMemcpyAsync(ctx->staging_out.ptr, ctx->dout.ptr, n_out * sizeof(double), hipMemcpyDeviceToHost,
@@ -905,6 +940,66 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
     if (n_h) std::memcpy(histo, o + n_c, n_h * sizeof(double));
     if (n_g) std::memcpy(grad, o + n_c + n_h, n_g * sizeof(double));
     if (n_m) std::memcpy(model, o + n_c + n_h + n_g, n_m * sizeof(double));
+  }
+  return MU_OK;
+}
+
+// Gradient pass and cost pass over one dataset with one merge launch.
+mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *pg,
+                              int32_t n_grad, const double *pc, int32_t n_cost, unsigned mem, double *cost_g,
+                              double *grad, double *cost_c) {
+  mu_status st = check_eval_args(ctx, cost_kind, mem, n_grad, pg);
+  if (st == MU_OK) st = check_eval_args(ctx, cost_kind, mem, n_cost, pc);
+  if (st != MU_OK) return st;
+  hipSetDevice(ctx->device);
+  const int n_par = th->h.n_par;
+  const size_t n_pg = (size_t)n_grad * n_par, n_pc = (size_t)n_cost * n_par;
+  const size_t n_out = (size_t)n_grad + (size_t)n_grad * n_par + (size_t)n_cost;
+  const double *dpg = pg, *dpc = pc;
+  double *dcg = cost_g, *dg = grad, *dcc = cost_c;
+  hipError_t e;
+  if (mem == MU_MEM_HOST) {
+    if ((st = ctx->dparams.ensure(ctx, (n_pg + n_pc) * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->dout.ensure(ctx, n_out * sizeof(double), false)) != MU_OK) return st;
+    if ((st = ctx->staging.ensure(ctx, (n_pg + n_pc) * sizeof(double))) != MU_OK) return st;
+    if ((st = ctx->staging_out.ensure(ctx, n_out * sizeof(double))) != MU_OK) return st;
+    ctx->wait_staging();
+    std::memcpy(ctx->staging.ptr, pg, n_pg * sizeof(double));
+    std::memcpy(static_cast<double *>(ctx->staging.ptr) + n_pg, pc, n_pc * sizeof(double));
+    e = hipMemcpyAsync(ctx->dparams.ptr, ctx->staging.ptr, (n_pg + n_pc) * sizeof(double), hipMemcpyHostToDevice,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(params)");
+    ctx->mark_staging();
+    dpg = static_cast<double *>(ctx->dparams.ptr);
+    dpc = dpg + n_pg;
+    dcg = static_cast<double *>(ctx->dout.ptr);
+    dg = dcg + n_grad;
+    dcc = dg + n_pg;
+  }
+  // both passes on the context's stream (their own slot buffers), then one
+  // merge launch for both: the gradient job's merge latency hides behind the
+  // cost jobs' merges
+  Pending pg_, pc_;
+  if ((st = eval_launch(ctx, d, th, cost_kind, dpg, n_grad, dcg, nullptr, dg, nullptr, kModeGrad, ctx->stream,
+                        ctx->partial_aux, pg_)) != MU_OK)
+    return st;
+  if ((st = eval_launch(ctx, d, th, cost_kind, dpc, n_cost, dcc, nullptr, nullptr, nullptr, kModeCost, ctx->stream,
+                        ctx->partial, pc_)) != MU_OK)
+    return st;
+  const int ti = ctx->time_begin(MU_TIME_MERGE, ctx->stream);
+  e = launch_merge_grad_cost(pg_.a, n_grad, pc_.a, n_cost, ctx->stream);
+  ctx->time_end(ti, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
+  if (mem == MU_MEM_HOST) {
+    e = hipMemcpyAsync(ctx->staging_out.ptr, ctx->dout.ptr, n_out * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(results)");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    const double *o = static_cast<const double *>(ctx->staging_out.ptr);
+    std::memcpy(cost_g, o, n_grad * sizeof(double));
+    std::memcpy(grad, o + n_grad, n_pg * sizeof(double));
+    std::memcpy(cost_c, o + n_grad + n_pg, n_cost * sizeof(double));
   }
   return MU_OK;
 }
@@ -936,6 +1031,21 @@ extern "C" mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_the
   }
   return eval_uniform(ctx, const_cast<mu_data *>(data), th, cost_kind, params, n_vec, mem, cost, nullptr, grad,
                       nullptr, kModeGrad);
+}
+
+extern "C" mu_status mu_chi2_eval_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                                       const double *params_grad, int32_t n_grad, const double *params_cost,
+                                       int32_t n_cost, unsigned mem, double *cost_grad, double *grad,
+                                       double *cost) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (!cost_grad || !grad || !cost) {
+    set_err(ctx, "cost_grad, grad and cost outputs must not be NULL");
+    return MU_E_ARG;
+  }
+  return eval_grad_and_costs(ctx, const_cast<mu_data *>(data), th, cost_kind, params_grad, n_grad, params_cost,
+                             n_cost, mem, cost_grad, grad, cost);
 }
 
 extern "C" mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th, const double *params,
@@ -1085,9 +1195,9 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     a.cost_kind = cost_kind;
     a.anchor_every = ctx->anchor_every;
     a.partial = static_cast<double *>(ctx->partial.ptr);
-    const int ti = ctx->time_begin(grad ? MU_TIME_EVAL_GRAD : MU_TIME_EVAL_COST);
+    const int ti = ctx->time_begin(grad ? MU_TIME_EVAL_GRAD : MU_TIME_EVAL_COST, ctx->stream);
     e = launch_eval(a, grad ? kModeGrad : kModeCost, data[0]->f64, shp, ctx->stream);
-    ctx->time_end(ti);
+    ctx->time_end(ti, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched evaluation launch");
   }
   {
@@ -1095,9 +1205,9 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     std::memset(&m, 0, sizeof m);
     m.jobs = reinterpret_cast<const DevJob *>(dup);
     m.partial = static_cast<double *>(ctx->partial.ptr);
-    const int ti = ctx->time_begin(MU_TIME_MERGE);
+    const int ti = ctx->time_begin(MU_TIME_MERGE, ctx->stream);
     e = launch_merge(m, grad ? kModeGrad : kModeCost, n_jobs, ctx->stream);
-    ctx->time_end(ti);
+    ctx->time_end(ti, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
   }
   if (mem == MU_MEM_HOST) {

@@ -457,8 +457,17 @@ struct SlotMap {
 
 template <int MODE>
 __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
-  __shared__ Pair red[kBlock / 64];
-  const int tid = threadIdx.x;
+  // Phase A issues every load that depends on nothing else (the slot span,
+  // the theory's resolved-scalar descriptors, the first chunk's histogram
+  // records); phase B issues the cost slots and the first chunk's gradient
+  // entries together. Later histogram chunks (more than HC histograms) add
+  // two rounds each.
+  constexpr int HC = 32;  // histograms per chunk
+  constexpr int kWaves = kBlock / 64;
+  __shared__ Pair red[kWaves];
+  __shared__ int span_s[2];
+  __shared__ int rk0[HC], rk1[HC], rrow[HC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   SlotMap sm;
   sm.J = &J;
   sm.W = (a.jobs == nullptr) ? a.split_w : 0;
@@ -466,51 +475,141 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   sm.vbase = (int64_t)job * a.total;
   sm.jbase = job * J.n_histo;
   const double *P = sm.P;
-  int s0, s1;
-  sm.span(s0, s1);
+  const DevTheory *th = J.th;
+  const int n_par = MODE == kModeGrad ? th->n_par : 0;
+  const bool need_chunks = MODE == kModeGrad || J.histo_out != nullptr;
 
-  // total cost: strided fixed assignment of slots to threads, then a tree
-  Pair acc{0.0, 0.0};
-  for (int k = s0 + tid; k < s1; k += kBlock) acc = pair_add(acc, Pair{P[(int64_t)k * kSlot], P[(int64_t)k * kSlot + 1]});
-  acc = wave_pair_sum(acc);
-  if ((tid & 63) == 0) red[tid >> 6] = acc;
-  __syncthreads();
-  if (tid == 0) {
-    Pair t = red[0];
-    for (int w = 1; w < kBlock / 64; ++w) t = pair_add(t, red[w]);
-    J.cost_out[0] = pair_value(t);
-  }
+  // chain rule through the map / function array (gradient mode):
+  //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's slots.
+  // Only the scalars the theory takes from p or f are kept (list `act`). For a
+  // chunk of histograms the entries e = (hh, i) hold gR and the map lookup
+  // (pidx >= 0: parameter index; <= -2: function -(2 + i); -1: none) in LDS;
+  // then one wave per parameter gathers its entries, lane-strided, and
+  // combines them with a fixed-shape tree, so the order never depends on timing.
+  __shared__ double gR[MODE == kModeGrad ? HC * kRS : 1];
+  __shared__ int pidx[MODE == kModeGrad ? HC * kRS : 1];
+  __shared__ int act[kRS], act_slot[kRS], act_fun[kRS];
+  __shared__ int n_act_s;
+  __shared__ double acc_s[MODE == kModeGrad ? MU_MAX_PAR : 1];
+  __shared__ double acc_c[MODE == kModeGrad ? MU_MAX_PAR : 1];
 
-  // per-histogram cost
-  if (J.histo_out) {
-    for (int h = tid; h < J.n_histo; h += kBlock) {
+  auto stage_ranges = [&](int h0) {
+    const int nh = min(HC, J.n_histo - h0);
+    for (int hh = tid; hh < nh; hh += kBlock) {
       int k0, k1;
-      sm.range(h, k0, k1);
-      J.histo_out[h] = sum_slot_pairs(P, k0, k1);
+      sm.range(h0 + hh, k0, k1);
+      rk0[hh] = k0;
+      rk1[hh] = k1;
+      rrow[hh] = J.histos[h0 + hh].map_row;
     }
-  }
+  };
+  // gradient entries and per-histogram costs of the staged chunk
+  auto chunk_entries = [&](int h0) {
+    const int nh = min(HC, J.n_histo - h0);
+    if (J.histo_out)
+      for (int hh = tid; hh < nh; hh += kBlock) J.histo_out[h0 + hh] = sum_slot_pairs(P, rk0[hh], rk1[hh]);
+    if constexpr (MODE == kModeGrad) {
+      const int na = n_act_s;
+      for (int e = tid; e < nh * na; e += kBlock) {
+        const int hh = e / na, i = e - hh * na;
+        const int m = th->map[rrow[hh] * th->n_slots + act_slot[i]];
+        gR[e] = sum_slots(P, rk0[hh], rk1[hh], 2 + act[i]);
+        pidx[e] = act_fun[i] ? -(2 + m) : m;
+      }
+    }
+  };
+  // Per parameter, its entries of the staged chunk in a fixed order: a
+  // counting sort by parameter (counts, exclusive scan, then each entry's
+  // rank among the earlier entries of its parameter), after which thread k
+  // sums its own contiguous run, then the function entries in entry order.
+  __shared__ int koff[MODE == kModeGrad ? MU_MAX_PAR + 1 : 1];
+  __shared__ double srt[MODE == kModeGrad ? HC * kRS : 1];
+  __shared__ int fun_e[MODE == kModeGrad ? HC * kRS : 1];
+  __shared__ int n_fun_s;
+  auto chunk_gather = [&](int h0) {
+    if constexpr (MODE == kModeGrad) {
+      const int ne = min(HC, J.n_histo - h0) * n_act_s;
+      for (int k = tid; k <= n_par; k += kBlock) koff[k] = 0;
+      if (tid == 0) n_fun_s = 0;
+      __syncthreads();
+      for (int e = tid; e < ne; e += kBlock) {
+        const int pi = pidx[e];
+        if (pi >= 0) atomicAdd(&koff[pi + 1], 1);  // counts only: the order of the adds does not matter
+      }
+      __syncthreads();
+      if (wave == 0) {
+        // inclusive scan of koff[1 .. n_par]: lane l owns a run of `per` values
+        const int per = (n_par + 63) / 64;
+        int run = 0;
+        for (int q = 0; q < per; ++q) {
+          const int k = lane * per + q + 1;
+          if (k <= n_par) run += koff[k];
+        }
+        int incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int v = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += v;
+        }
+        int base = incl - run;
+        for (int q = 0; q < per; ++q) {
+          const int k = lane * per + q + 1;
+          if (k <= n_par) {
+            base += koff[k];
+            koff[k] = base;
+          }
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < ne; e += kBlock) {
+        const int pi = pidx[e];
+        if (pi == -1) continue;
+        // rank among the earlier entries of the same parameter (or among the
+        // earlier function entries): eight independent reads per step
+        const bool fun = pi <= -2;
+        int rank = 0, e2 = 0;
+        for (; e2 + 8 <= e; e2 += 8) {
+          int v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = pidx[e2 + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) rank += fun ? (v[u] <= -2) : (v[u] == pi);
+        }
+        for (; e2 < e; ++e2) rank += fun ? (pidx[e2] <= -2) : (pidx[e2] == pi);
+        if (fun) {
+          fun_e[rank] = e;
+          atomicAdd(&n_fun_s, 1);
+        } else {
+          srt[koff[pi] + rank] = gR[e];
+        }
+      }
+      __syncthreads();
+      const int nf = n_fun_s;
+      for (int k = tid; k < n_par; k += kBlock) {
+        Pair q{acc_s[k], acc_c[k]};
+        for (int j = koff[k]; j < koff[k + 1]; ++j) q = pair_add(q, Pair{srt[j], 0.0});
+        for (int f = 0; f < nf; ++f) {
+          const int e = fun_e[f];
+          q = pair_add(q, Pair{gR[e] * th->F[(int64_t)(-2 - pidx[e]) * n_par + k], 0.0});
+        }
+        acc_s[k] = q.s;
+        acc_c[k] = q.c;
+      }
+    }
+  };
 
+  // ---- phase A
+  if (tid == 0) {
+    int k0, k1;
+    sm.range(0, k0, k1);
+    span_s[0] = k0;
+  }
+  if (tid == 64) {
+    int k0, k1;
+    sm.range(J.n_histo - 1, k0, k1);
+    span_s[1] = k1;
+  }
   if constexpr (MODE == kModeGrad) {
-    // chain rule through the map / function array:
-    //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's tiles.
-    // Only the scalars the theory takes from p or f are kept (list `act`). For a
-    // chunk of histograms the entries e = (hh, i) hold gR and the map lookup
-    // (pidx >= 0: parameter index; <= -2: function -(2 + i); -1: none) in LDS;
-    // then one wave per parameter gathers its entries, lane-strided, and
-    // combines them with a fixed-shape tree, so the order never depends on timing.
-    constexpr int HC = 32;
-    constexpr int kWaves = kBlock / 64;
-    __shared__ double gR[HC * kRS];
-    __shared__ int pidx[HC * kRS];
-    __shared__ int act[kRS];
-    __shared__ int act_slot[kRS];
-    __shared__ int act_fun[kRS];
-    __shared__ int n_act_s;
-    __shared__ double acc_s[MU_MAX_PAR];
-    __shared__ double acc_c[MU_MAX_PAR];
-    const DevTheory *th = J.th;
-    const int n_par = th->n_par;
-    const int lane = tid & 63, wave = tid >> 6;
     if (wave == 0) {
       // compaction in order of r: lane r keeps its scalar at the rank of r
       // among the active ones
@@ -530,40 +629,36 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
       acc_s[k] = 0.0;
       acc_c[k] = 0.0;
     }
+  }
+  if (need_chunks) stage_ranges(0);
+  __syncthreads();
+
+  // ---- phase B: total cost (strided fixed assignment of slots to threads,
+  // then a tree) and the first chunk
+  Pair acc{0.0, 0.0};
+  for (int k = span_s[0] + tid; k < span_s[1]; k += kBlock)
+    acc = pair_add(acc, Pair{P[(int64_t)k * kSlot], P[(int64_t)k * kSlot + 1]});
+  if (need_chunks) chunk_entries(0);
+  acc = wave_pair_sum(acc);
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    Pair t = red[0];
+    for (int w = 1; w < kWaves; ++w) t = pair_add(t, red[w]);
+    J.cost_out[0] = pair_value(t);
+  }
+  if (!need_chunks) return;
+  chunk_gather(0);
+  for (int h0 = HC; h0 < J.n_histo; h0 += HC) {
+    __syncthreads();  // the previous chunk's entries are consumed
+    stage_ranges(h0);
     __syncthreads();
-    const int na = n_act_s;
-    for (int h0 = 0; h0 < J.n_histo; h0 += HC) {
-      const int nh = min(HC, J.n_histo - h0);
-      const int ne = nh * na;
-      for (int e = tid; e < ne; e += kBlock) {
-        const int hh = e / na, i = e - hh * na;
-        const int h = h0 + hh;
-        int k0, k1;
-        sm.range(h, k0, k1);
-        const int m = th->map[J.histos[h].map_row * th->n_slots + act_slot[i]];
-        gR[e] = sum_slots(P, k0, k1, 2 + act[i]);
-        pidx[e] = act_fun[i] ? -(2 + m) : m;
-      }
-      __syncthreads();
-      for (int k = wave; k < n_par; k += kWaves) {
-        Pair q{0.0, 0.0};
-        for (int e = lane; e < ne; e += 64) {
-          const int pi = pidx[e];
-          if (pi == k) {
-            q = pair_add(q, Pair{gR[e], 0.0});
-          } else if (pi <= -2) {
-            q = pair_add(q, Pair{gR[e] * th->F[(int64_t)(-2 - pi) * n_par + k], 0.0});
-          }
-        }
-        q = wave_pair_sum(q);
-        if (lane == 0) {
-          const Pair t = pair_add(Pair{acc_s[k], acc_c[k]}, q);
-          acc_s[k] = t.s;
-          acc_c[k] = t.c;
-        }
-      }
-      __syncthreads();
-    }
+    chunk_entries(h0);
+    __syncthreads();
+    chunk_gather(h0);
+  }
+  if constexpr (MODE == kModeGrad) {
+    __syncthreads();
     for (int k = tid; k < n_par; k += kBlock) J.grad_out[k] = pair_value(Pair{acc_s[k], acc_c[k]});
   }
 }
@@ -1034,12 +1129,11 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
   }
 }
 
-// One workgroup per job: fixed-order merge of the job's tile slots.  It runs
-// as its own launch after the evaluation kernel, whose completion makes every
+// One workgroup per job: fixed-order merge of the job's slots.  It runs as
+// its own launch after the evaluation kernel, whose completion makes every
 // slot visible; no fences or atomics are needed inside the evaluation kernel.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void merge_kernel(LaunchArgs a) {
-  int job = blockIdx.x;
+__device__ __forceinline__ void merge_block(const LaunchArgs &a, int job) {
   DevJob J;
   if (a.jobs == nullptr) {
     J = a.tmpl;
@@ -1052,6 +1146,21 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(LaunchArgs a) {
     J = a.jobs[job];
   }
   merge_job<MODE>(a, J, job);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void merge_kernel(LaunchArgs a) {
+  merge_block<MODE>(a, blockIdx.x);
+}
+
+// Merges of two launches in one: workgroups [0, n_first) merge the jobs of
+// `first` (mode M0), the rest those of `second` (mode M1).
+template <int M0, int M1>
+__global__ __launch_bounds__(kBlock) void merge2_kernel(LaunchArgs first, int n_first, LaunchArgs second) {
+  if ((int)blockIdx.x < n_first)
+    merge_block<M0>(first, blockIdx.x);
+  else
+    merge_block<M1>(second, blockIdx.x - n_first);
 }
 
 template <int COST, int MODE, typename Sh>
@@ -1107,6 +1216,13 @@ hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s
     hipLaunchKernelGGL((merge_kernel<kModeGrad>), grid, block, 0, s, a);
   else
     hipLaunchKernelGGL((merge_kernel<kModeCost>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, hipStream_t s) {
+  if (n_grad <= 0 || n_cost <= 0) return hipErrorInvalidValue;
+  dim3 grid(n_grad + n_cost), block(kBlock);
+  hipLaunchKernelGGL((merge2_kernel<kModeGrad, kModeCost>), grid, block, 0, s, g, n_grad, c);
   return hipGetLastError();
 }
 

@@ -121,5 +121,7 @@ hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, 
 int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape);
 // Merge the tile slots of jobs [0, n_jobs) of `a` (uniform or mapped).
 hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s);
+// One launch merging a gradient launch's n_grad jobs and a cost launch's n_cost jobs.
+hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, hipStream_t s);
 
 }  // namespace mu

@@ -40,6 +40,9 @@ mu_status check_pair(mu_ctx *ctx, const mu_data *d, const mu_theory *th);
 mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *params,
                        int32_t n_vec, unsigned mem, double *cost, double *histo, double *grad, double *model,
                        int mode);
+// The same with device pointers only, on stream s with partial slots `partial`.
+mu_status eval_dev(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp, int32_t n_vec,
+                   double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s, DevBuf &partial);
 struct TileSet;
 mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
                     const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
@@ -66,7 +69,8 @@ struct mu_ctx {
   int64_t pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const;
   int specialize = 1;  // use the compiled shape kernels when a theory matches one
   hipEvent_t staging_free = nullptr;  // recorded after each upload from `staging`
-  mu::DevBuf partial, dparams, dout, djobs;
+  // partial_aux: the gradient pass's slots in mu_chi2_eval_grad
+  mu::DevBuf partial, partial_aux, dparams, dout, djobs;
   mu::HostBuf staging, staging_out;
   std::vector<mu::DevBuf> extra;
   void release_all();
@@ -79,8 +83,9 @@ struct mu_ctx {
   };
   std::vector<Timed> timed;
   // Records the start event of a timed launch; returns the index to close, or -1.
-  int time_begin(int kind);
-  void time_end(int idx);
+  int time_begin(int kind, hipStream_t s);
+  void time_end(int idx, hipStream_t s);
+
   // Wait until the last upload from `staging` has been consumed.
   void wait_staging() {
     if (staging_free) hipEventSynchronize(staging_free);

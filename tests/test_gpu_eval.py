@@ -376,3 +376,33 @@ def test_kernel_timing_records_each_launch(ctx):
     ctx.timing(True)
     assert ctx.timing_read("cost") == (0, 0.0)
     ctx.timing(False)
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_eval_grad_overlapped_matches_separate_calls(ctx, kind):
+    """The overlapped gradient + cost call equals the separate calls bit for
+    bit (same kernels and launch shapes), on host and device memory, and its
+    stencil costs match the oracle."""
+    import torch
+    _say("eval_grad overlapped", kind)
+    cfg, counts = c2()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p0 = perturbed(cfg["p_true"], 1e-3, 51)
+    P = np.stack([perturbed(cfg["p_true"], 1e-3, 60 + v) for v in range(9)])
+    cg, g, cc = api.chi2_eval_grad(ctx, d, th, p0, P, kind)
+    sg, sgg = api.chi2_grad(ctx, d, th, p0, kind)
+    sc = api.chi2_eval(ctx, d, th, P, kind)
+    np.testing.assert_array_equal(cg, sg)
+    np.testing.assert_array_equal(g, sgg)
+    np.testing.assert_array_equal(cc, sc)
+    for v in (0, 8):
+        ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v], kind)
+        assert abs(cc[v] - ref) <= REL * ref
+    dev = torch.device("cuda:0")
+    with torch.cuda.stream(ctx.torch_stream):
+        tcg, tg, tcc = api.chi2_eval_grad(ctx, d, th, torch.tensor(p0[None], device=dev),
+                                          torch.tensor(P, device=dev), kind)
+        torch.cuda.synchronize()
+    np.testing.assert_array_equal(tcg.cpu().numpy(), cg)
+    np.testing.assert_array_equal(tg.cpu().numpy(), g)
+    np.testing.assert_array_equal(tcc.cpu().numpy(), cc)

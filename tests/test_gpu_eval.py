@@ -406,3 +406,121 @@ def test_eval_grad_overlapped_matches_separate_calls(ctx, kind):
     np.testing.assert_array_equal(tcg.cpu().numpy(), cg)
     np.testing.assert_array_equal(tg.cpu().numpy(), g)
     np.testing.assert_array_equal(tcc.cpu().numpy(), cc)
+
+
+def _stencil(p, rel=1e-4):
+    rows = []
+    for k in range(p.size):
+        h = rel * max(abs(p[k]), 1.0)
+        for sgn in (1.0, -1.0):
+            q = p.copy()
+            q[k] += sgn * h
+            rows.append(q)
+    return np.array(rows)
+
+
+def test_bench_launch_configuration_sampled(ctx):
+    """The launch the benchmark times: C2 (16 x 65536 bins), the 104-vector
+    central-difference stencil at 65536 bins per workgroup and anchors every
+    256 steps, plus the gradient at the centre in the same call. Sampled
+    stencil vectors against the oracle one by one, every vector against the
+    default launch shape to rounding."""
+    _say("bench launch configuration")
+    cfg, counts = c2()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    p0 = cfg["p_true"] * (1.0 + 1e-3 * np.cos(np.arange(cfg["p_true"].size)))
+    S = _stencil(p0)
+    assert S.shape == (104, 52)
+    default = api.chi2_eval(ctx, d, th, S)
+    try:
+        ctx.tile, ctx.anchor = 65536, 256
+        cg, g, cc = api.chi2_eval_grad(ctx, d, th, p0, S)
+    finally:
+        ctx.tile, ctx.anchor = 0, 0
+    assert np.all(np.abs(cc - default) <= 1e-13 * default)
+    for v in (0, 37, 88, 103):
+        ref = model.cost(cfg["theory"], cfg["histos"], counts, S[v])
+        assert abs(cc[v] - ref) <= REL * ref, (v, cc[v], ref)
+    ref_g = model.grad(cfg["theory"], cfg["histos"], counts, p0)
+    scale = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, p0)
+    assert np.all(np.abs(g[0] - ref_g) <= REL * scale)
+    assert abs(cg[0] - model.cost(cfg["theory"], cfg["histos"], counts, p0)) <= REL * cg[0]
+
+
+def test_split_ranges_cross_histogram_and_vector_boundaries(ctx):
+    """Uneven fit ranges and bins-per-workgroup values that divide nothing:
+    workgroup ranges start inside histograms, cover several histograms and
+    cross from one vector to the next; costs, per-histogram costs and
+    gradients of every vector against the oracle."""
+    _say("split ranges")
+    th_d = synth.theory_c2(n_det=3)
+    hs = [{"n_bins": 6000, "dt": 0.0005, "t0_bin": 0.0, "first": 17, "last": 5016, "map_row": 0},
+          {"n_bins": 900, "dt": 0.001, "t0_bin": 2.0, "first": 0, "last": 776, "map_row": 1},
+          {"n_bins": 13000, "dt": 0.0002, "t0_bin": 0.0, "first": 300, "last": 12644, "map_row": 2}]
+    p = np.array([0.2, 0.5, 1.355, 0.3, 900.0, 2.0, 0.1, 1500.0, 1.0, 2.0, 700.0, 3.0, -1.0])
+    counts = counts_for(th_d, hs, p, np.random.default_rng(71))
+    th, d = _mk(ctx, th_d, hs, counts)
+    P = np.stack([perturbed(p, 1e-2, 80 + v) for v in range(7)])
+    refs = [model.cost(th_d, hs, counts, P[v]) for v in range(7)]
+    refs_h = [model.cost_per_histo(th_d, hs, counts, P[v]) for v in range(7)]
+    ref_g = [model.grad(th_d, hs, counts, P[v]) for v in range(7)]
+    scales = [model.grad_abs_scale(th_d, hs, counts, P[v]) for v in range(7)]
+    try:
+        for W in (256, 300, 777, 1000, 5000, 18122, 20000, 100000):
+            ctx.tile = W
+            c, ph = api.chi2_eval(ctx, d, th, P, per_histo=True)
+            cg, g = api.chi2_grad(ctx, d, th, P)
+            for v in range(7):
+                assert abs(c[v] - refs[v]) <= REL * refs[v], (W, v)
+                assert np.all(np.abs(ph[v] - refs_h[v]) <= REL * np.abs(refs_h[v])), (W, v)
+                assert abs(cg[v] - refs[v]) <= REL * refs[v], (W, v)
+                assert np.all(np.abs(g[v] - ref_g[v]) <= REL * scales[v]), (W, v)
+    finally:
+        ctx.tile = 0
+
+
+def test_reciprocal_table_boundary_counts(ctx):
+    """Integer counts around the size of the per-workgroup reciprocal table
+    (2048) and far above it, interleaved so that one wave mixes table reads
+    with the hardware-reciprocal path; zeros take v = 1."""
+    _say("reciprocal table boundary")
+    th_d = synth.theory_exp_cos()
+    pattern = np.array([0, 1, 2, 3, 2046, 2047, 2048, 2049, 2050, 4095, 65535, 1000000, 16777216, 123456789, 7, 0])
+    n = 50000
+    cts = np.resize(pattern, n).astype(np.float64)
+    hs = [{"n_bins": n, "dt": 0.0002, "t0_bin": 0.0, "first": 0, "last": n - 1, "map_row": 0}]
+    th, d = _mk(ctx, th_d, hs, [cts])
+    assert d.is_f64 is False  # every value is an integer below 2^32: 32-bit storage
+    p = np.array([3000.0, 5.0, 0.2, 0.7, 3.3, 0.4])
+    P = np.stack([p, perturbed(p, 0.1, 90)])
+    got = api.chi2_eval(ctx, d, th, P)
+    cg, g = api.chi2_grad(ctx, d, th, P)
+    for v in range(2):
+        ref = model.cost(th_d, hs, [cts], P[v])
+        assert abs(got[v] - ref) <= REL * ref
+        assert abs(cg[v] - ref) <= REL * ref
+        rg = model.grad(th_d, hs, [cts], P[v])
+        sc = model.grad_abs_scale(th_d, hs, [cts], P[v])
+        assert np.all(np.abs(g[v] - rg) <= REL * sc)
+
+
+def test_eval_grad_argument_errors(ctx):
+    _say("eval_grad errors")
+    import ctypes as C
+    from paper_1604_02334_amd import _abi as A
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    L = A.lib()
+    p = np.ascontiguousarray(cfg["p_true"][None])
+    out = np.zeros(8)
+    g = np.zeros((1, 6))
+    ok = L.mu_chi2_eval_grad(ctx.h, d.h, th.h, 0, p.ctypes.data, 1, p.ctypes.data, 1, A.MU_MEM_HOST,
+                             out.ctypes.data, g.ctypes.data, out[1:].ctypes.data)
+    assert ok == A.MU_OK
+    assert L.mu_chi2_eval_grad(ctx.h, d.h, th.h, 0, p.ctypes.data, 1, p.ctypes.data, 0, A.MU_MEM_HOST,
+                               out.ctypes.data, g.ctypes.data, out[1:].ctypes.data) == A.MU_E_ARG
+    assert L.mu_chi2_eval_grad(ctx.h, d.h, th.h, 0, p.ctypes.data, 1, p.ctypes.data, 1, A.MU_MEM_HOST,
+                               out.ctypes.data, None, out[1:].ctypes.data) == A.MU_E_ARG
+    assert L.mu_chi2_eval_grad(ctx.h, d.h, th.h, 7, p.ctypes.data, 1, p.ctypes.data, 1, A.MU_MEM_HOST,
+                               out.ctypes.data, g.ctypes.data, out[1:].ctypes.data) == A.MU_E_ARG
+    assert b"cost" in L.mu_ctx_last_error(ctx.h)

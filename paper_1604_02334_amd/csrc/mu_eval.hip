@@ -44,6 +44,7 @@ namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kThird = 1.0 / 3.0;
+constexpr double kInvPi = 0.318309886183790671537767526745;  // 1 / pi
 constexpr double kTwoThird = 2.0 / 3.0;
 constexpr int kSlots = kMaxT * kMaxFT;
 
@@ -112,25 +113,6 @@ __device__ __forceinline__ double pair_value(Pair x) { return isinf(x.s) ? x.s :
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
-__device__ __forceinline__ Pair wave_pair_sum(Pair p) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    Pair o{shfl_xor_d(p.s, m), shfl_xor_d(p.c, m)};
-    // both lanes of a pair combine (lower lane, upper lane): identical results
-    p = ((threadIdx.x & m) == 0) ? pair_add(p, o) : pair_add(o, p);
-  }
-  return p;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    double o = shfl_xor_d(v, m);
-    v = ((threadIdx.x & m) == 0) ? (v + o) : (o + v);
-  }
-  return v;
-}
-
 // Uniform copy of lane `src`'s value (scalar registers).
 __device__ __forceinline__ double bcast(double v, int src) {
   const long long bits = __double_as_longlong(v);
@@ -138,6 +120,57 @@ __device__ __forceinline__ double bcast(double v, int src) {
   const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+
+// Partner value through a DPP lane move (VALU, no LDS round trip): CTRL is a
+// DPP control of the row (16 lanes): quad_perm [1,0,3,2] (0xB1), quad_perm
+// [2,3,0,1] (0x4E), row_half_mirror (0x141), row_mirror (0x140).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Compensated sum over the wave, the same in every lane. Within a row of 16
+// lanes: partner lanes 1 apart, then 2 (quad swaps), then the other half of
+// the group of 8 (half mirror), then of the row (mirror); after each step all
+// lanes of a group hold the same pair, and the pair holding the lower lanes
+// is always the left operand, so both partners compute identical results.
+// The four row results are then combined in a fixed order.
+__device__ __forceinline__ Pair wave_pair_sum(Pair p) {
+  const int lane = threadIdx.x & 63;
+  {
+    const Pair o{dpp_d<0xB1>(p.s), dpp_d<0xB1>(p.c)};
+    p = (lane & 1) ? pair_add(o, p) : pair_add(p, o);
+  }
+  {
+    const Pair o{dpp_d<0x4E>(p.s), dpp_d<0x4E>(p.c)};
+    p = (lane & 2) ? pair_add(o, p) : pair_add(p, o);
+  }
+  {
+    const Pair o{dpp_d<0x141>(p.s), dpp_d<0x141>(p.c)};
+    p = (lane & 4) ? pair_add(o, p) : pair_add(p, o);
+  }
+  {
+    const Pair o{dpp_d<0x140>(p.s), dpp_d<0x140>(p.c)};
+    p = (lane & 8) ? pair_add(o, p) : pair_add(p, o);
+  }
+  const Pair r0{bcast(p.s, 0), bcast(p.c, 0)}, r1{bcast(p.s, 16), bcast(p.c, 16)};
+  const Pair r2{bcast(p.s, 32), bcast(p.c, 32)}, r3{bcast(p.s, 48), bcast(p.c, 48)};
+  return pair_add(pair_add(r0, r1), pair_add(r2, r3));
+}
+
+// Plain sum over the wave, the same in every lane (addition is commutative,
+// so partners agree without ordering).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
+}
+
 
 // Wave-uniform copies of values that are the same in every lane (scalar
 // registers): for loads the compiler cannot prove uniform, e.g. after the
@@ -163,9 +196,10 @@ __device__ __forceinline__ DevHisto uni(DevHisto x) {
 // Out-of-line transcendentals: they run at anchors and in the workgroup
 // prologue, and one copy each keeps the kernels small.
 __device__ __attribute__((noinline)) double x_exp(double x) { return exp(x); }
-__device__ __attribute__((noinline)) D2 x_sincos(double x) {
+// cos and sin of pi x: the phase is reduced in half-cycles, exactly
+__device__ __attribute__((noinline)) D2 x_sincospi(double x) {
   D2 r;
-  sincos(x, &r.b, &r.a);  // a = cos, b = sin
+  sincospi(x, &r.b, &r.a);  // a = cos, b = sin
   return r;
 }
 // stretched exponential e^(-(l t)^b) and (l t)^b ln(l t)
@@ -208,7 +242,7 @@ __device__ __forceinline__ double step_const(int kind, int w, double a0, double 
       return w == 0 ? x_exp(-(x * x)) : 0.0;
     }
     case MU_TF: {
-      const D2 cs = x_sincos(kTwoPi * a1 * h);
+      const D2 cs = x_sincospi(2.0 * a1 * h);  // angle 2 pi nu h
       return w == 0 ? cs.a : cs.b;
     }
     default:
@@ -231,7 +265,8 @@ __device__ __forceinline__ void anchor(int kind, double t, double a0, double a1,
       break;
     }
     case MU_TF: {
-      const D2 cs = x_sincos(kTwoPi * a1 * t + a0);
+      // angle 2 pi nu t + phi, in half-cycles
+      const D2 cs = x_sincospi(fma(2.0 * a1, t, a0 * kInvPi));
       s0 = cs.a;
       s1 = cs.b;
       break;

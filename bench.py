@@ -187,6 +187,19 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     pp, _, rp = api.fit_batch(ctx, [datas[j] for j in sub], [ths[j] for j in sub], start[sub],
                               analytic_grad=False, batched=False, want_cov=False)
     tp = time.perf_counter() - t0
+    # fits that spent their budget: how many sit in a degenerate valley
+    # (condition of the correlation matrix from the covariance above 1e6)
+    ill = 0
+    for j, r in enumerate(rb):
+        if r["status"] != 0:
+            n = sets[j]["start"].size
+            c = covb[j][:n, :n]
+            dg = np.sqrt(np.abs(np.diag(c)))
+            if np.all(dg > 0) and np.all(np.isfinite(c)):
+                cond = np.linalg.cond(c / np.outer(dg, dg))
+                ill += bool(not np.isfinite(cond) or cond > 1e6)
+            else:
+                ill += 1
     agree = 0
     for k, j in enumerate(sub):
         n = sets[j]["start"].size
@@ -197,6 +210,7 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     return {"datasets": n_sets, "bins": int(bins),
             "batched": {"fits": n_sets, "seconds": round(tb, 3), "fits_per_s": round(n_sets / tb, 2),
                         "converged": int(sum(r["status"] == 0 for r in rb)),
+                        "unconverged_ill_conditioned": ill,
                         "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in rb])), 1)},
             "batched_subset": {"fits": n_plain, "seconds": round(tb2, 3), "fits_per_s": round(n_plain / tb2, 2)},
             "plain_subset": {"fits": n_plain, "seconds": round(tp, 3), "fits_per_s": round(n_plain / tp, 2),

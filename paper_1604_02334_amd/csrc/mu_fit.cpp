@@ -33,6 +33,7 @@ using namespace mu;
 namespace {
 
 enum Phase { kStart, kHessInit, kIter, kLine, kHessPolish, kPolish, kDone };
+constexpr int kRefresh = 50;  // variable-metric steps between Hessian refreshes of an unconverged fit
 
 struct Point {
   std::vector<double> p;  // full parameter vector
@@ -87,6 +88,7 @@ struct Fit {
   double f = 0.0, gd = 0.0, alpha = 1.0, edm = 0.0, last_step = 1e300;
   int phase = kStart;
   int n_iter = 0, n_fcn = 0, n_grad = 0, status = 0, tries = 0, polish_iter = 0;
+  int refreshed = -1;  // iteration of the last Hessian refresh
   std::vector<Point> posts;
 
   std::vector<double> full(const std::vector<double> &xf) const {
@@ -129,16 +131,27 @@ struct Fit {
       }
     return A;
   }
+  // V = A^-1. An indefinite A (away from the minimum) is made positive
+  // definite by a diagonal shift mu |A_kk|, mu growing tenfold from 1e-3,
+  // which keeps its correlations; the diagonal alone is the last resort.
   void set_v_from(const std::vector<double> &A) {
     std::vector<double> L = A;
     if (cholesky(L, n)) {
       V = spd_inverse(L, n);
-    } else {
-      V.assign(n * n, 0.0);
-      for (int k = 0; k < n; ++k) {
-        const double h = std::fabs(A[k * n + k]);
-        V[k * n + k] = h > 0.0 && std::isfinite(h) ? 1.0 / h : 1e-6 * std::max(x[k] * x[k], 1.0);
+      return;
+    }
+    for (double mu = 1e-3; mu <= 1e3; mu *= 10.0) {
+      L = A;
+      for (int k = 0; k < n; ++k) L[k * n + k] += mu * std::fabs(A[k * n + k]);
+      if (cholesky(L, n)) {
+        V = spd_inverse(L, n);
+        return;
       }
+    }
+    V.assign(n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+      const double h = std::fabs(A[k * n + k]);
+      V[k * n + k] = h > 0.0 && std::isfinite(h) ? 1.0 / h : 1e-6 * std::max(x[k] * x[k], 1.0);
     }
   }
   void direction() {
@@ -386,6 +399,15 @@ struct FitDriver {
       return;
     }
     F.direction();
+    // a fit that has not converged after kRefresh steps gets a fresh Hessian
+    // (by differences of the gradient) in place of the variable metric
+    if (F.n_iter > 0 && F.n_iter % kRefresh == 0 && F.refreshed != F.n_iter && F.edm >= o.tol_edm &&
+        F.n_iter < o.max_iter) {
+      F.refreshed = F.n_iter;
+      F.post_hessian();
+      F.phase = kHessInit;
+      return;
+    }
     if (F.edm < o.tol_edm || (F.n_iter > 0 && F.last_step < o.tol_step_rel) || F.n_iter >= o.max_iter) {
       if (F.n_iter >= o.max_iter && F.edm >= o.tol_edm) F.status = 1;
       if (o.polish) {

@@ -99,6 +99,25 @@ using ShapeStg = ShapeFixed<1, 1, MU_STG, 0, 0, 0, 0>;
 using ShapeExpStg = ShapeFixed<2, 1, MU_SE, 0, 1, MU_STG, 0>;
 using ShapeExpCosStg = ShapeFixed<2, 2, MU_SE, MU_TF, 1, MU_STG, 0>;
 
+// Exponentials an anchor of a compiled shape needs: the lifetime, one per
+// exponential factor, two per Gaussian factor (state and ratio).
+template <typename Sh>
+constexpr int anchor_exps() {
+  if constexpr (!Sh::kFixed) {
+    return 1;
+  } else {
+    TStruct ts{};
+    int n = 1;
+    for (int kt = 0; kt < Sh::nt(ts); ++kt)
+      for (int f = 0; f < Sh::nf(ts, kt); ++f) {
+        const int p = Sh::prim(ts, kt, f);
+        n += p == MU_SE ? 1 : (p == MU_SG || p == MU_STG) ? 2 : 0;
+      }
+    return n;
+  }
+}
+
+
 // Knuth's TwoSum applied to two compensated pairs.
 __device__ __forceinline__ Pair pair_add(Pair x, Pair y) {
   double s = x.s + y.s;
@@ -200,6 +219,18 @@ __device__ __attribute__((noinline)) double x_exp(double x) { return exp(x); }
 __device__ __attribute__((noinline)) D2 x_sincospi(double x) {
   D2 r;
   sincospi(x, &r.b, &r.a);  // a = cos, b = sin
+  return r;
+}
+// N exponentials in one call: the evaluations are independent and interleave.
+template <int N>
+struct DN {
+  double v[N];
+};
+template <int N>
+__device__ __attribute__((noinline)) DN<N> x_expn(DN<N> x) {
+  DN<N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.v[i] = exp(x.v[i]);
   return r;
 }
 // stretched exponential e^(-(l t)^b) and (l t)^b ln(l t)
@@ -752,21 +783,45 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   // uniform step constants, one transcendental per lane of every wave, then
   // broadcast within the wave: lane 0: lifetime ratio; lane 1 + 2 s + w:
   // constant w of factor slot s
+  // every lane first forms its argument, then the wave makes one exp call
+  // and one sincospi call (masked), not one call per primitive kind
   double cst = 0.0;
-  if (lane == 0) {
-    cst = x_exp(neg_inv_tau * h);
-  } else if (lane <= 2 * kSlots) {
-    const int s = (lane - 1) >> 1, w = (lane - 1) & 1;
-    const int k = s / kMaxFT, f = s % kMaxFT;
-    if (k < n_terms && f < Sh::nf(ts, k)) {
-      double a0 = 0.0, a1 = 0.0;
+  {
+    double earg = 0.0, parg = 0.0;
+    bool e_on = false, p_on = false;
+    const int w = (lane - 1) & 1;
+    if (lane == 0) {
+      earg = neg_inv_tau * h;
+      e_on = true;
+    } else if (lane <= 2 * kSlots) {
+      const int s = (lane - 1) >> 1;
+      const int k = s / kMaxFT, f = s % kMaxFT;
+      if (k < n_terms && f < Sh::nf(ts, k)) {
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q)
-        if (q == s) {
-          a0 = R[kArg0 + 2 * q];
-          a1 = R[kArg0 + 2 * q + 1];
+        for (int q = 0; q < kSlots; ++q)
+          if (q == s) {
+            a0 = R[kArg0 + 2 * q];
+            a1 = R[kArg0 + 2 * q + 1];
+          }
+        const int kind = Sh::prim(ts, k, f);
+        if (kind == MU_SE && w == 0) {
+          earg = -a0 * h;
+          e_on = true;
+        } else if ((kind == MU_SG || kind == MU_STG) && w == 0) {
+          const double x = a0 * h;
+          earg = -(x * x);
+          e_on = true;
+        } else if (kind == MU_TF) {
+          parg = 2.0 * a1 * h;  // angle 2 pi nu h
+          p_on = true;
         }
-      cst = step_const(Sh::prim(ts, k, f), w, a0, a1, h);
+      }
+    }
+    if (e_on) cst = x_exp(earg);
+    if (p_on) {
+      const D2 cs = x_sincospi(parg);
+      cst = w == 0 ? cs.a : cs.b;
     }
   }
   const double rE = bcast(cst, 0);
@@ -975,14 +1030,57 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   for (int k0 = 0; k0 < n_max; k0 += every) {
     // exact re-evaluation (anchor) at the first step of the segment
     t = fma((double)k0, h, t_first);
-    const double life = x_exp(neg_inv_tau * t);
+    double life;
+    if constexpr (Sh::kFixed) {
+      // the shape's exponentials (lifetime, exponential and Gaussian states)
+      // in one call; anchor() below then only places them
+      constexpr int kNE = anchor_exps<Sh>();
+      DN<kNE> ea;
+      int q = 0;
+      ea.v[q++] = neg_inv_tau * t;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int kt = s / kMaxFT, f = s % kMaxFT;
+        if (kt < n_terms && f < Sh::nf(ts, kt)) {
+          const int p = Sh::prim(ts, kt, f);
+          const double a0 = R[kArg0 + 2 * s];
+          if (p == MU_SE) ea.v[q++] = -a0 * t;
+          if (p == MU_SG || p == MU_STG) {
+            const double x = a0 * t;
+            ea.v[q++] = -0.5 * (x * x);
+            ea.v[q++] = -(a0 * a0) * h * (t + 0.5 * h);
+          }
+        }
+      }
+      ea = x_expn<kNE>(ea);
+      q = 0;
+      life = ea.v[q++];
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int kt = s / kMaxFT, f = s % kMaxFT;
+        if (kt < n_terms && f < Sh::nf(ts, kt)) {
+          const int p = Sh::prim(ts, kt, f);
+          if (p == MU_SE) {
+            s0[s] = ea.v[q++];
+            s1[s] = 0.0;
+          }
+          if (p == MU_SG || p == MU_STG) {
+            s0[s] = ea.v[q++];
+            s1[s] = ea.v[q++];
+          }
+        }
+      }
+    } else {
+      life = x_exp(neg_inv_tau * t);
+    }
     E = kScaled ? ecoef * life : life;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
       const int kt = s / kMaxFT, f = s % kMaxFT;
       if (kt < n_terms && f < Sh::nf(ts, kt)) {
         const int p = Sh::prim(ts, kt, f);
-        anchor(p, t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
+        if (!Sh::kFixed || p == MU_TF || p == MU_GE)
+          anchor(p, t, R[kArg0 + 2 * s], R[kArg0 + 2 * s + 1], h, s0[s], s1[s]);
         if constexpr (kScaled) {
           if (p == MU_STG) {
             u[s] = R[kArg0 + 2 * s] * t;

@@ -524,3 +524,32 @@ def test_eval_grad_argument_errors(ctx):
     assert L.mu_chi2_eval_grad(ctx.h, d.h, th.h, 7, p.ctypes.data, 1, p.ctypes.data, 1, A.MU_MEM_HOST,
                                out.ctypes.data, g.ctypes.data, out[1:].ctypes.data) == A.MU_E_ARG
     assert b"cost" in L.mu_ctx_last_error(ctx.h)
+
+
+def test_split_launch_many_histograms_unstaged(ctx):
+    """More histograms than a split launch stages in LDS (256): the
+    prologue reads offsets and map rows from memory; costs and gradients of
+    several vectors against the oracle."""
+    _say("split launch, 300 histograms")
+    th_d = synth.theory_exp_cos()
+    n_h = 300
+    hs = [{"n_bins": 150 + (j % 7) * 13, "dt": 0.002, "t0_bin": 0.0, "first": 0, "last": 149 + (j % 7) * 13,
+           "map_row": 0} for j in range(n_h)]
+    p = np.array([800.0, 2.0, 0.2, 0.5, 3.0, 0.3])
+    counts = counts_for(th_d, hs, p, np.random.default_rng(123))
+    th, d = _mk(ctx, th_d, hs, counts)
+    P = np.stack([perturbed(p, 1e-2, 130 + v) for v in range(3)])
+    try:
+        for W in (0, 1000, 7777):
+            ctx.tile = W
+            c = api.chi2_eval(ctx, d, th, P)
+            cg, g = api.chi2_grad(ctx, d, th, P)
+            for v in range(3):
+                ref = model.cost(th_d, hs, counts, P[v])
+                assert abs(c[v] - ref) <= REL * ref, (W, v)
+                assert abs(cg[v] - ref) <= REL * ref, (W, v)
+                rg = model.grad(th_d, hs, counts, P[v])
+                sc = model.grad_abs_scale(th_d, hs, counts, P[v])
+                assert np.all(np.abs(g[v] - rg) <= REL * sc), (W, v)
+    finally:
+        ctx.tile = 0

@@ -174,6 +174,12 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     for j, s in enumerate(sets):
         start[j, :s["start"].size] = s["start"]
     bins = sum(d.n_bins for d in datas)
+    # one pass, one vector per dataset (cost only), in one batched launch
+    api.chi2_batch(ctx, datas, ths, start)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        api.chi2_batch(ctx, datas, ths, start)
+    t_pass = (time.perf_counter() - t0) / 5
     _log(f"c4: {n_sets} datasets, {bins} bins; batched fits")
     t0 = time.perf_counter()
     pb, covb, rb = api.fit_batch(ctx, datas, ths, start)
@@ -208,6 +214,8 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     for d in datas:
         d.close()
     return {"datasets": n_sets, "bins": int(bins),
+            "single_pass": {"ms": round(t_pass * 1e3, 3), "gbin_s": round(bins / t_pass / 1e9, 1),
+                            "note": "host parameters and results, one launch per theory shape + merge"},
             "batched": {"fits": n_sets, "seconds": round(tb, 3), "fits_per_s": round(n_sets / tb, 2),
                         "converged": int(sum(r["status"] == 0 for r in rb)),
                         "unconverged_ill_conditioned": ill,
@@ -217,6 +225,158 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
                              "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in rp])), 1),
                              "same_minimum_as_batched": agree},
             "speedup_batched_vs_plain_subset": round(tp / tb2, 1)}
+
+
+def _wall_us(fn, reps, sync):
+    """Mean wall-clock microseconds per call of fn(), synchronised after each."""
+    for _ in range(3):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+        sync()
+    return (time.perf_counter() - t0) / reps * 1e6
+
+
+def _data_from_model(api, ctx, theory, histos, p, rng):
+    """Counts drawn from the library's model values (synthetic inputs)."""
+    import synth
+
+    th = api.Theory(ctx, theory)
+    grid = api.Data(ctx, histos, [np.zeros(h["n_bins"]) for h in histos])
+    means = api.model_eval(ctx, grid, th, p)
+    grid.close()
+    n = histos[0]["n_bins"]
+    counts = synth.draw_counts(means, rng).reshape(len(histos), n)
+    return th, api.Data(ctx, histos, list(counts)), counts
+
+
+def _default_start(counts, dt, tau=2.1969811, win=256):
+    """Start without a model fit: N0 and Nbkg from the means of the first and
+    last `win` bins (lifetime decay plus background), A 0.175, lambda 0.5,
+    nu sqrt(5) MHz, phi 0."""
+    n = counts.size
+    t1, t2 = (win / 2.0) * dt, (n - win / 2.0) * dt
+    m1, m2 = counts[:win].mean(), counts[-win:].mean()
+    e1, e2 = math.exp(-t1 / tau), math.exp(-t2 / tau)
+    n0 = max((m1 - m2) / (e1 - e2), 1.0)
+    return np.array([n0, max(m2 - n0 * e2, 0.0), 0.175, 0.5, math.sqrt(5.0), 0.0])
+
+
+def _c1_latency(api, ctx):
+    """C1: single-evaluation latency (host and device memory) and whole fits."""
+    import torch
+    import synth
+
+    cfg = synth.config_c1()
+    th, d, counts = _data_from_model(api, ctx, cfg["theory"], cfg["histos"], cfg["p_true"],
+                                     synth.rng_for(cfg["seed_k"]))
+    p = cfg["p_true"][None]
+    pd = torch.tensor(p, dtype=torch.float64, device="cuda")
+    sync = torch.cuda.synchronize
+    out = {"bins": int(d.n_bins)}
+    out["chi2_host_us"] = round(_wall_us(lambda: api.chi2_eval(ctx, d, th, p), 50, sync), 2)
+    out["poisson_host_us"] = round(_wall_us(lambda: api.chi2_eval(ctx, d, th, p, "poisson"), 50, sync), 2)
+    with torch.cuda.stream(ctx.torch_stream):
+        out["chi2_device_us"] = round(_wall_us(lambda: api.chi2_eval(ctx, d, th, pd), 50, sync), 2)
+        out["chi2_grad_device_us"] = round(_wall_us(lambda: api.chi2_grad(ctx, d, th, pd), 50, sync), 2)
+    for name, start in (("truth", cfg["p_true"]), ("default", _default_start(counts[0], cfg["histos"][0]["dt"]))):
+        t0 = time.perf_counter()
+        pf, _, r = api.fit_batch(ctx, [d], [th], start[None], want_cov=False)
+        out[f"fit_from_{name}"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "n_fcn": r[0]["n_fcn"],
+                                   "status": r[0]["status"], "cost": r[0]["cost"]}
+    d.close()
+    return out
+
+
+def _c2_large(api, ctx, n_vec=8):
+    """The 16-detector theory over 16 x 2^23 bins (537 MB of counts, beyond the
+    256 MB MALL): one launch of n_vec vectors streams the counts n_vec times."""
+    import torch
+    import synth
+
+    cfg = synth.config_c2_large()
+    _log("c2-large: drawing 16 x 2^23 counts")
+    th, d, _ = _data_from_model(api, ctx, cfg["theory"], cfg["histos"], cfg["p_true"], cfg["rng"])
+    P = torch.tensor(cfg["p_true"][None] * (1.0 + 1e-4 * np.arange(n_vec)[:, None]), dtype=torch.float64,
+                     device="cuda")
+    with torch.cuda.stream(ctx.torch_stream):
+        api.chi2_eval(ctx, d, th, P)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        for _ in range(3):
+            api.chi2_eval(ctx, d, th, P)
+        torch.cuda.synchronize()
+        ctx.timing(False)
+    n, ms = ctx.timing_read("cost")
+    bins = n_vec * d.n_bins
+    rate = bins / (ms / n * 1e-3)
+    out = {"bins_per_vector": int(d.n_bins), "vectors": n_vec, "kernel_ms": round(ms / n, 3),
+           "gbin_s": round(rate / 1e9, 1), "count_stream_gb_s": round(BYTES_PER_BIN * rate / 1e9, 1),
+           "hbm_frac_if_streamed": round(BYTES_PER_BIN * rate / 1e9 / PEAK_HBM_GBS, 3)}
+    d.close()
+    return out
+
+
+def _c3_stencils(api, ctx):
+    """C3: 4096 vectors around the C1 truth: cost and gradient of all in one
+    launch, against 4096 separate gradient calls and against the numerical
+    stencil (2P + 1 cost evaluations per vector) in one launch."""
+    import torch
+    import synth
+
+    cfg = synth.config_c3()
+    th, d, _ = _data_from_model(api, ctx, cfg["theory"], cfg["histos"], cfg["p_true"],
+                                synth.rng_for(cfg["seed_k"]))
+    P = torch.tensor(cfg["P"], dtype=torch.float64, device="cuda")
+    nv, npar = P.shape
+    h = 1e-6 * torch.clamp(P.abs(), min=1e-2)
+    St = [P]
+    for k in range(npar):
+        for sgn in (1.0, -1.0):
+            Q = P.clone()
+            Q[:, k] += sgn * h[:, k]
+            St.append(Q)
+    S = torch.cat(St, 0).contiguous()
+    sync = torch.cuda.synchronize
+    out = {"vectors": nv, "bins": int(d.n_bins)}
+    with torch.cuda.stream(ctx.torch_stream):
+        t = _wall_us(lambda: api.chi2_grad(ctx, d, th, P), 10, sync)
+        out["grad_one_launch_us"] = round(t, 1)
+        out["grad_one_launch_gbin_s"] = round(nv * d.n_bins / (t * 1e-6) / 1e9, 1)
+        rows = [P[i:i + 1] for i in range(nv)]
+
+        def separate():
+            for r in rows:
+                api.chi2_grad(ctx, d, th, r)
+        out["grad_separate_calls_us"] = round(_wall_us(separate, 2, sync), 1)
+        t = _wall_us(lambda: api.chi2_eval(ctx, d, th, S), 5, sync)
+        out["numeric_stencil_one_launch_us"] = round(t, 1)
+    out["speedup_vs_separate"] = round(out["grad_separate_calls_us"] / out["grad_one_launch_us"], 1)
+    out["speedup_vs_numeric"] = round(out["numeric_stencil_one_launch_us"] / out["grad_one_launch_us"], 2)
+    d.close()
+    return out
+
+
+def _paper_shape(api, ctx):
+    """Eq. 4 over 16 detectors at the smallest and largest Table 1 sizes: time
+    per cost evaluation and per cost + gradient (one vector, device memory)."""
+    import torch
+    import synth
+
+    out = {}
+    sync = torch.cuda.synchronize
+    for n_bins in (85320, 426601):
+        cfg = synth.config_paper_shape(n_bins)
+        th, d, _ = _data_from_model(api, ctx, cfg["theory"], cfg["histos"], cfg["p_true"], cfg["rng"])
+        p = torch.tensor(cfg["p_true"][None], dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(ctx.torch_stream):
+            te = _wall_us(lambda: api.chi2_eval(ctx, d, th, p), 50, sync)
+            tg = _wall_us(lambda: api.chi2_grad(ctx, d, th, p), 50, sync)
+        out[f"16x{n_bins}"] = {"bins": int(d.n_bins), "cost_us": round(te, 1), "cost_grad_us": round(tg, 1)}
+        d.close()
+    return out
 
 
 def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_plain=100):
@@ -443,6 +603,13 @@ def main():
     stream_ctx.__exit__(None, None, None)
     _log(f"step: {value:.1f} Gbin/s")
     if not args.no_fits:
+        _log("c1 latency and fits")
+        out["c1"] = _c1_latency(api, ctx)
+        out["c2_large"] = _c2_large(api, ctx)
+        _log("c3 stencils")
+        out["c3"] = _c3_stencils(api, ctx)
+        _log("paper-shape sizes")
+        out["paper_shape_eq4"] = _paper_shape(api, ctx)
         out["fits_c4"] = _fits_c4(api, ctx)
         out["seeder_c5"] = _seeder_c5(api, ctx)
     if not args.no_cpu:

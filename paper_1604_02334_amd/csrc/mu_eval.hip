@@ -245,10 +245,13 @@ __device__ __attribute__((noinline)) double x_pow(double x, double y) { return p
 
 // ------------------------------------------------------------------ resolve
 
-__device__ double resolve_ref(const DevTheory *th, DevRef r, const double *p, int row) {
+// Resolved scalar of reference r for parameter vector p and map row `row`;
+// f_s: the function values, when already formed.
+__device__ double resolve_ref(const DevTheory *th, DevRef r, const double *p, int row, const double *f_s) {
   if (r.kind == MU_REF_PAR) return p[th->map[row * th->n_slots + r.slot]];
   if (r.kind == MU_REF_FUN) {
     const int i = th->map[row * th->n_slots + r.slot];
+    if (f_s) return f_s[i];
     const double *Fi = th->F + (int64_t)i * th->n_par;
     double s = 0.0;
     for (int k = 0; k < th->n_par; ++k) s = fma(Fi[k], p[k], s);
@@ -773,7 +776,26 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   // resolves scalar r, then each is broadcast to scalar registers
   double R[kRS];
   {
-    const double mine = lane < kRS ? resolve_ref(th, th->rref[lane], S.p, row) : 0.0;
+    // the theory's functions f = F p + f0 (Sec. 4.2.1), once per segment: wave
+    // 0 forms each dot product lane-parallel with a fixed-order sum and
+    // shares them through LDS (a serial loop per scalar would wait on n_par
+    // loads)
+    __shared__ double f_s[kFunStage];
+    const int n_fun = __builtin_amdgcn_readfirstlane(th->n_fun);
+    const bool f_staged = n_fun > 0 && n_fun <= kFunStage;
+    if (f_staged) {
+      if (tid < 64) {
+        const int n_par = th->n_par;
+        for (int i = 0; i < n_fun; ++i) {
+          double acc = 0.0;
+          for (int k = lane; k < n_par; k += 64) acc = fma(th->F[(int64_t)i * n_par + k], S.p[k], acc);
+          acc = wave_sum(acc);
+          if (lane == 0) f_s[i] = acc + th->f0[i];
+        }
+      }
+      __syncthreads();
+    }
+    const double mine = lane < kRS ? resolve_ref(th, th->rref[lane], S.p, row, f_staged ? f_s : nullptr) : 0.0;
 #pragma unroll
     for (int r = 0; r < kRS; ++r) R[r] = bcast(mine, r);
   }

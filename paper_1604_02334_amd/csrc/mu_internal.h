@@ -22,6 +22,9 @@ constexpr int kPrefetch = 4;
 // Entries of the per-workgroup table of 1 / max(d, 1) for integer counts
 // d < kInvTab (chi^2 kernels; FP64, 16 KiB of LDS).
 constexpr int kInvTab = 2048;
+// Functions of p formed once per segment and shared through LDS (more use the
+// per-scalar path).
+constexpr int kFunStage = 32;
 // Partial slot of one tile: cost (s, c) then kRS gradient components.
 constexpr int kSlot = 2 + kRS;  // 32 doubles
 constexpr int kBlock = 256;     // threads per evaluation workgroup

@@ -553,3 +553,64 @@ def test_split_launch_many_histograms_unstaged(ctx):
                 assert np.all(np.abs(g[v] - rg) <= REL * sc), (W, v)
     finally:
         ctx.tile = 0
+
+
+def _theory_multi_function(n_det=3):
+    """exp*cos per detector with every phase a function of two parameters
+    (phi_j = phi0 + j dphi + 0.1 j) and the frequency a function of two more
+    (nu = 13.553879 B + 0.5 dnu + 0.01): n_det + 1 functions, each row of F
+    with two non-zero entries, plus offsets f0."""
+    from synth.recipes import TAU_MU
+    n_par = 6 + 2 * n_det  # [A, lambda, B, dnu, phi0, dphi] + [N0_j, Nbkg_j]
+    F = []
+    f0 = []
+    for j in range(n_det):
+        row = [0.0] * n_par
+        row[4], row[5] = 1.0, float(j)
+        F.append(row)
+        f0.append(0.1 * j)
+    row = [0.0] * n_par
+    row[2], row[3] = 13.553879, 0.5
+    F.append(row)
+    f0.append(0.01)
+    rows = [[6 + 2 * j, 7 + 2 * j, 0, 1, j, n_det] for j in range(n_det)]
+    return {"tau_mu": TAU_MU, "n0": ("p", 0), "nbkg": ("p", 1),
+            "terms": [{"coef": 1.0, "amp": ("p", 2),
+                       "factors": [{"prim": "se", "args": [("p", 3)]},
+                                   {"prim": "tf", "args": [("f", 4), ("f", 5)]}]}],
+            "map": rows, "F": F, "f0": f0, "n_par": n_par,
+            "names": ["A", "lambda", "B", "dnu", "phi0", "dphi"] + sum(([f"N0_{j}", f"Nbkg_{j}"] for j in range(n_det)), [])}
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_function_array_references(ctx, kind):
+    """Scalars taken from the function array f = F p + f0 (Sec. 4.2.1,
+    Listing 3): Eq. 4 with the frequency a function of the field, and a theory
+    whose phases and frequency are functions of several parameters. Costs,
+    per-histogram costs and gradients (chain rule through F) against the
+    oracle."""
+    _say("function array", kind)
+    th1 = synth.theory_paper_eq4(n_det=4)
+    p1 = np.zeros(th1["n_par"])
+    p1[0], p1[1] = 0.35, 1.0
+    for j in range(4):
+        p1[2 + 4 * j: 6 + 4 * j] = [900.0 + 100 * j, 3.0, 0.25, 2 * math.pi * j / 4]
+    hs1 = [{"n_bins": 3000, "dt": 0.004, "t0_bin": 0.0, "first": 0, "last": 2999, "map_row": j} for j in range(4)]
+    th2 = _theory_multi_function(3)
+    p2 = np.array([0.2, 0.6, 0.1, 0.4, 0.3, 0.7, 1000.0, 2.0, 800.0, 4.0, 1200.0, 1.0])
+    hs2 = [{"n_bins": 2500, "dt": 0.004, "t0_bin": 0.0, "first": 0, "last": 2499, "map_row": j} for j in range(3)]
+    for th_d, hs, p, seed in ((th1, hs1, p1, 140), (th2, hs2, p2, 141)):
+        counts = counts_for(th_d, hs, p, np.random.default_rng(seed))
+        th, d = _mk(ctx, th_d, hs, counts)
+        P = np.stack([perturbed(p, 1e-2, seed + v) for v in range(3)])
+        c, ph = api.chi2_eval(ctx, d, th, P, kind, per_histo=True)
+        cg, g = api.chi2_grad(ctx, d, th, P, kind)
+        for v in range(3):
+            ref = model.cost(th_d, hs, counts, P[v], kind)
+            assert abs(c[v] - ref) <= REL * ref, (th_d["names"][:3], v)
+            assert abs(cg[v] - ref) <= REL * ref
+            rh = model.cost_per_histo(th_d, hs, counts, P[v], kind)
+            assert np.all(np.abs(ph[v] - rh) <= REL * np.abs(rh))
+            rg = model.grad(th_d, hs, counts, P[v], kind)
+            sc = model.grad_abs_scale(th_d, hs, counts, P[v], kind)
+            assert np.all(np.abs(g[v] - rg) <= REL * sc), (th_d["names"][:3], v, np.max(np.abs(g[v] - rg) / sc))

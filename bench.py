@@ -463,7 +463,7 @@ def main():
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the timed stencil launches (for hardware-counter runs)")
     ap.add_argument("--tile", type=int, default=0,
-                    help="with --stencil-only: bins per workgroup (skips the autotuner; 0 keeps it)")
+                    help="with --stencil-only: bins per wave (skips the autotuner; 0 keeps it)")
     ap.add_argument("--anchor", type=int, default=0, help="with --stencil-only and --tile: anchor interval")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
@@ -501,7 +501,7 @@ def main():
     stream_ctx.__enter__()
 
     def step():
-        # gradient pass and stencil pass in one call: they overlap on two streams
+        # gradient pass, stencil pass and one combined merge in one call
         return api.chi2_eval_grad(ctx, data, th, p_dev, s_dev)
 
     if args.stencil_only and args.tile:

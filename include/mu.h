@@ -214,16 +214,17 @@ mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data,
 mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
                         const double *params, unsigned mem, double *out);
 
-/* Bins per workgroup used by evaluation launches on this context.
+/* Bins per work unit used by evaluation launches on this context; the unit
+ * is one 64-lane wave (four share a workgroup).
  * Single-dataset launches (mu_chi2_eval, mu_chi2_grad, mu_model_eval) cut the
- * n_vec x bins work into equal ranges of this many bins, one per workgroup,
+ * n_vec x bins work into equal ranges of this many bins, one per wave,
  * across histogram and vector boundaries; batched launches (mu_chi2_batch,
  * the fitter) cut each histogram into tiles of this size.  0 (default): per
  * launch, the choice mu_autotune measured for the same theory shape, mode,
  * cost and size (to a power of two), else for single-dataset launches one
- * range per resident workgroup (at least 256 bins) and for batched launches
- * about four workgroups per compute unit with tiles of 1024 .. 65536 bins.
- * Otherwise any value in [256, 2^26].  Results depend on it only through the
+ * range per resident wave (at least 64 bins) and for batched launches
+ * about sixteen waves per compute unit with tiles of 1024 .. 65536 bins.
+ * Otherwise any value in [64, 2^26].  Results depend on it only through the
  * rounding order of the sums. */
 mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins);
 int32_t mu_ctx_get_tile(const mu_ctx *ctx);
@@ -263,9 +264,9 @@ mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable);
 mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_launches, double *total_ms);
 
 /* Measure the evaluation of n_vec vectors over `data` (cost, or cost and
- * gradient when grad != 0) for several bins-per-workgroup values (powers of
+ * gradient when grad != 0) for several bins-per-wave values (powers of
  * two from 1024 to 65536, and the values that give 1, 2, 3, 4, 6 or 8
- * workgroups per resident slot) and anchor intervals 32 .. 256, keep
+ * waves per resident wave slot) and anchor intervals 32 .. 256, keep
  * candidates whose costs agree with the first to 1e-12 relative, and
  * remember the fastest for later single-dataset launches of the same theory
  * shape, mode, cost and size (to a power of two) while the tile size is 0.

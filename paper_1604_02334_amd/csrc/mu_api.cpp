@@ -250,8 +250,8 @@ extern "C" mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins) {
     ctx->tile_bins = 0;
     return MU_OK;
   }
-  if (tile_bins < kBlock || tile_bins > kMaxSplit) {
-    set_err(ctx, "tile_bins must be 0 or in [%d, %d]", kBlock, kMaxSplit);
+  if (tile_bins < kWave || tile_bins > kMaxSplit) {
+    set_err(ctx, "tile_bins must be 0 or in [%d, %d]", kWave, kMaxSplit);
     return MU_E_ARG;
   }
   ctx->tile_bins = tile_bins;
@@ -392,8 +392,8 @@ void mu_data::free_dev() {
 }
 
 // Tile size for a launch: the tuned choice for this (shape, mode, cost, size)
-// if one was measured, else about four workgroups per compute unit with
-// tiles of 1024 .. 65536 bins.
+// if one was measured, else about four workgroups (sixteen waves) per compute
+// unit with tiles of 1024 .. 65536 bins.
 // Key of the tuned table: theory shape, mode, cost, launch kind (tile or
 // split) and the size of the launch to a power of two.
 static int tune_key(int shape, int mode, int cost, int split, int64_t work) {
@@ -411,12 +411,12 @@ int64_t mu_ctx::pick_split(int shape, int mode, int cost, int count_f64, int64_t
       *anchor = t.anchor;
       return t.tile;
     }
-  // one range per resident workgroup of the cost kernel (the same ranges for
-  // the cost and the gradient pass, so their costs agree bit for bit), at
-  // least one bin per lane
+  // one range per resident wave of the cost kernel (the same ranges for the
+  // cost and the gradient pass, so their costs agree bit for bit), at least
+  // one bin per lane
   const int per_cu = eval_blocks_per_cu(kModeCost, cost, count_f64, shape);
-  const int64_t cap = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
-  return std::max<int64_t>(kBlock, (work + cap - 1) / cap);
+  const int64_t cap = (int64_t)std::max(per_cu, 1) * (kBlock / kWave) * std::max(n_cu, 1);
+  return std::max<int64_t>(kWave, (work + cap - 1) / cap);
 }
 
 int mu_ctx::pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const {
@@ -428,7 +428,8 @@ int mu_ctx::pick_tile(int shape, int mode, int cost, int64_t work, int64_t longe
       *anchor = t.anchor;
       return t.tile;
     }
-  int64_t want = work / (4 * std::max(n_cu, 1));
+  // about four resident workgroups (of kBlock / kWave waves) per compute unit
+  int64_t want = work / (4 * (kBlock / kWave) * std::max(n_cu, 1));
   int tile = kMinTile;
   while (tile < kMaxTile && (int64_t)tile * 2 <= want) tile *= 2;
   // no tile longer than the longest histogram needs
@@ -831,14 +832,14 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   const int64_t work = (int64_t)n_vec * d->total;
   const int64_t W = ctx->pick_split(shape, mode, cost_kind, d->f64, work, &anchor);
   const int n_par = th->h.n_par;
-  const int64_t n_blocks = (work + W - 1) / W;
-  if (n_blocks + (int64_t)n_vec * d->n_histo > INT32_MAX) {
-    set_err(ctx, "launch needs more than 2^31 workgroups");
+  const int64_t n_units = (work + W - 1) / W;
+  if (n_units + (int64_t)n_vec * d->n_histo > INT32_MAX) {
+    set_err(ctx, "launch needs more than 2^31 work units");
     return MU_E_UNSUPPORTED;
   }
   if (mode != kModeModel) {
-    // slot b + v * n_histo + h for every segment (see the split launch)
-    const size_t n_slots = (size_t)n_blocks + (size_t)n_vec * d->n_histo;
+    // slot u + v * n_histo + h for every segment (see the split launch)
+    const size_t n_slots = (size_t)n_units + (size_t)n_vec * d->n_histo;
     if ((st = partial.ensure(ctx, n_slots * kSlot * sizeof(double), false)) != MU_OK) return st;
   }
   LaunchArgs a;
@@ -858,8 +859,8 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   a.grad_stride = n_par;
   a.histo_stride = d->n_histo;
   a.jobs = nullptr;
-  a.block_job = nullptr;
-  a.n_blocks = (int32_t)n_blocks;
+  a.unit_job = nullptr;
+  a.n_units = (int32_t)n_units;
   a.cost_kind = cost_kind;
   a.anchor_every = anchor;
   a.n_vec = n_vec;
@@ -1100,35 +1101,35 @@ extern "C" mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *c
   int anchor = ctx->anchor_every;
   const int tile = ctx->pick_tile(kShapeGeneric, grad ? kModeGrad : kModeCost, cost_kind, work, longest, &anchor);
   std::vector<const TileSet *> sets(n_jobs);
-  int64_t n_blocks = 0;
+  int64_t n_units = 0;
   for (int j = 0; j < n_jobs; ++j) {
     if ((st = const_cast<mu_data *>(data[j])->tiles(tile, &sets[j])) != MU_OK) return st;
-    n_blocks += sets[j]->n_tiles;
+    n_units += sets[j]->n_tiles;
   }
-  if (n_blocks > INT32_MAX) {
-    set_err(ctx, "launch needs more than 2^31 workgroups");
+  if (n_units > INT32_MAX) {
+    set_err(ctx, "launch needs more than 2^31 work units");
     return MU_E_UNSUPPORTED;
   }
-  return run_batch(ctx, n_jobs, data, sets.data(), th, cost_kind, ld, params, mem, cost, grad, n_blocks, anchor);
+  return run_batch(ctx, n_jobs, data, sets.data(), th, cost_kind, ld, params, mem, cost, grad, n_units, anchor);
 }
 
 namespace mu {
 
 mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
                     const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
-                    double *cost, double *grad, int64_t n_blocks, int anchor) {
+                    double *cost, double *grad, int64_t n_units, int anchor) {
   mu_status st;
   hipError_t e;
   const size_t n_p = (size_t)n_jobs * ld;
   const size_t n_c = (size_t)n_jobs;
   const size_t n_g = grad ? (size_t)n_jobs * ld : 0;
   const size_t jobs_bytes = (size_t)n_jobs * sizeof(DevJob);
-  const size_t map_bytes = (size_t)n_blocks * sizeof(int32_t);
+  const size_t map_bytes = (size_t)n_units * sizeof(int32_t);
   const size_t meta = ((jobs_bytes + map_bytes + 255) & ~size_t(255));
   const size_t up_bytes = meta + (mem == MU_MEM_HOST ? n_p * sizeof(double) : 0);
   if ((st = ctx->djobs.ensure(ctx, up_bytes, false)) != MU_OK) return st;
   if ((st = ctx->staging.ensure(ctx, up_bytes)) != MU_OK) return st;
-  if ((st = ctx->partial.ensure(ctx, (size_t)n_blocks * kSlot * sizeof(double), false)) != MU_OK) return st;
+  if ((st = ctx->partial.ensure(ctx, (size_t)n_units * kSlot * sizeof(double), false)) != MU_OK) return st;
   if (mem == MU_MEM_HOST) {
     if ((st = ctx->dout.ensure(ctx, (n_c + n_g) * sizeof(double), false)) != MU_OK) return st;
     if ((st = ctx->staging_out.ensure(ctx, (n_c + n_g) * sizeof(double))) != MU_OK) return st;
@@ -1148,8 +1149,8 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     dc = static_cast<double *>(ctx->dout.ptr);
     dg = grad ? dc + n_c : nullptr;
   }
-  // jobs keep their order (and partial slots); workgroups are grouped by
-  // theory shape so each group runs its compiled specialisation
+  // jobs keep their order (and partial slots); units are grouped by theory
+  // shape so each group runs its compiled specialisation
   int32_t slot_base = 0;
   for (int j = 0; j < n_jobs; ++j) {
     DevJob &J = jobs[j];
@@ -1175,7 +1176,7 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     for (int j = 0; j < n_jobs; ++j) {
       const int js = ctx->specialize ? th[j]->shape : kShapeGeneric;
       if (js != shp) continue;
-      jobs[j].block_base = filled - group_first[shp];
+      jobs[j].unit_base = filled - group_first[shp];
       for (int k = 0; k < jobs[j].n_tiles; ++k) bj[filled + k] = j;
       filled += jobs[j].n_tiles;
     }
@@ -1190,8 +1191,8 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     LaunchArgs a;
     std::memset(&a, 0, sizeof a);
     a.jobs = reinterpret_cast<const DevJob *>(dup);
-    a.block_job = reinterpret_cast<const int32_t *>(dup + jobs_bytes) + group_first[shp];
-    a.n_blocks = nb;
+    a.unit_job = reinterpret_cast<const int32_t *>(dup + jobs_bytes) + group_first[shp];
+    a.n_units = nb;
     a.cost_kind = cost_kind;
     a.anchor_every = ctx->anchor_every;
     a.partial = static_cast<double *>(ctx->partial.ptr);
@@ -1262,17 +1263,17 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   int64_t bt = 0;
   int ba = 0;
   float best = 1e30f;
-  // candidates (bins per workgroup of the split launch): whole multiples of
-  // the resident workgroup count (every workgroup of a round equally loaded),
-  // and powers of two
+  // candidates (bins per wave of the split launch): whole multiples of the
+  // resident wave count (every wave of a round equally loaded), and powers of
+  // two
   std::vector<int64_t> cand;
   const int64_t work_all = (int64_t)n_vec * d->total;
   {
     const int shape = ctx->specialize ? th->shape : kShapeGeneric;
     const int per_cu = eval_blocks_per_cu(mode, cost_kind, d->f64, shape);
-    const int64_t cap = (int64_t)std::max(per_cu, 1) * std::max(ctx->n_cu, 1);
+    const int64_t cap = (int64_t)std::max(per_cu, 1) * (kBlock / kWave) * std::max(ctx->n_cu, 1);
     for (int m : {1, 2, 3, 4, 6, 8}) {
-      const int64_t w = std::max<int64_t>(kBlock, (work_all + m * cap - 1) / (m * cap));
+      const int64_t w = std::max<int64_t>(kWave, (work_all + m * cap - 1) / (m * cap));
       if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
     }
     for (int64_t w = kMinTile; w <= kMaxTile && w < work_all; w *= 2)

@@ -443,10 +443,10 @@ __device__ __forceinline__ DevJob job_of(const LaunchArgs &a, int b, int &job) {
     if (J.histo_out) J.histo_out += job * a.histo_stride;
     if (J.grad_out) J.grad_out += job * a.grad_stride;
     J.tile_base = job * a.tmpl.n_tiles;
-    J.block_base = J.tile_base;
+    J.unit_base = J.tile_base;
     return J;
   }
-  job = a.block_job[b];
+  job = a.unit_job[b];
   return a.jobs[job];
 }
 
@@ -500,7 +500,7 @@ __device__ double sum_slot_pairs(const double *P, int k0, int k1) {
 struct SlotMap {
   const double *P;
   const DevJob *J;
-  int64_t W, vbase;  // split launch: bins per workgroup, first bin of the vector
+  int64_t W, vbase;  // split launch: bins per unit, first bin of the vector
   int jbase;         // split launch: v * n_histo
   __device__ void range(int h, int &k0, int &k1) const {
     if (W == 0) {
@@ -780,27 +780,28 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     // 0 forms each dot product lane-parallel with a fixed-order sum and
     // shares them through LDS (a serial loop per scalar would wait on n_par
     // loads)
-    __shared__ double f_s[kFunStage];
+    __shared__ double f_all[kBlock / kWave][kFunStage];
+    double *f_s = f_all[tid / kWave];  // this wave's copy
     const int n_fun = __builtin_amdgcn_readfirstlane(th->n_fun);
     const bool f_staged = n_fun > 0 && n_fun <= kFunStage;
     if (f_staged) {
-      if (tid < 64) {
-        const int n_par = th->n_par;
-        for (int i = 0; i < n_fun; ++i) {
-          double acc = 0.0;
-          for (int k = lane; k < n_par; k += 64) acc = fma(th->F[(int64_t)i * n_par + k], S.p[k], acc);
-          acc = wave_sum(acc);
-          if (lane == 0) f_s[i] = acc + th->f0[i];
-        }
+      const int n_par = th->n_par;
+      for (int i = 0; i < n_fun; ++i) {
+        double acc = 0.0;
+        for (int k = lane; k < n_par; k += kWave) acc = fma(th->F[(int64_t)i * n_par + k], S.p[k], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) f_s[i] = acc + th->f0[i];
       }
-      __syncthreads();
+      // the wave's own LDS writes precede its reads (in-order per wave);
+      // this keeps the compiler from moving them across each other
+      __builtin_amdgcn_wave_barrier();
     }
     const double mine = lane < kRS ? resolve_ref(th, th->rref[lane], S.p, row, f_staged ? f_s : nullptr) : 0.0;
 #pragma unroll
     for (int r = 0; r < kRS; ++r) R[r] = bcast(mine, r);
   }
   const double n0 = R[0], nbkg = R[1];
-  const double h = S.dt * (double)kBlock;  // lane step
+  const double h = S.dt * (double)kWave;  // lane step
 
   // uniform step constants, one transcendental per lane of every wave, then
   // broadcast within the wave: lane 0: lifetime ratio; lane 1 + 2 s + w:
@@ -894,20 +895,20 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 #pragma unroll
   for (int r = 0; r < kRS; ++r) g[r] = 0.0;
 
-  const int64_t n_first = S.first + S.begin + tid;  // this lane's first bin
+  const int64_t n_first = S.first + S.begin + lane;  // this lane's first bin
   const double t_first = ((double)n_first - S.t0_bin) * S.dt;
   // every lane has n_full bins; lanes below S.n % 256 have one more
   const int seg_n = __builtin_amdgcn_readfirstlane(S.n);  // wave-uniform: scalar loop control
-  const int n_full = seg_n / kBlock;
-  const bool extra = tid < (seg_n % kBlock);
-  const int n_max = n_full + ((seg_n % kBlock) != 0 ? 1 : 0);
+  const int n_full = seg_n / kWave;
+  const bool extra = lane < (seg_n % kWave);
+  const int n_max = n_full + ((seg_n % kWave) != 0 ? 1 : 0);
   // FP32 storage holds integer counts only (the host checks), FP64 any value
   constexpr bool kIntData = sizeof(CT) == 4;
   // Counts are read kPrefetch lane steps ahead of their use, into a ring of
   // registers: dq[i] holds the count of the next step k with k % kPrefetch ==
   // i. Reads past a lane's last bin stay inside the counts buffer, which the
   // host pads by kPrefetch steps. Values stay in the storage type until use.
-  const int64_t idx0 = S.off + S.begin + tid;
+  const int64_t idx0 = S.off + S.begin + lane;
   typedef const __attribute__((address_space(1))) CT *GlobalCT;  // global loads, not flat
   const GlobalCT cp = (GlobalCT)(static_cast<const CT *>(S.counts) + idx0);
   CT dq[kPrefetch];
@@ -915,7 +916,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   for (int i = 0; i < kPrefetch; ++i) dq[i] = CT(0);
   if constexpr (MODE != kModeModel) {
 #pragma unroll
-    for (int i = 0; i < kPrefetch; ++i) dq[i] = cp[(int64_t)i * kBlock];
+    for (int i = 0; i < kPrefetch; ++i) dq[i] = cp[(int64_t)i * kWave];
   }
   // anchors at multiples of kPrefetch steps keep the ring aligned
   const int every = (S.anchor_every + kPrefetch - 1) / kPrefetch * kPrefetch;
@@ -929,7 +930,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     return 0.0;
   };
   auto bin_step = [&](int k, double d_cur, double iv) {
-    const int64_t idx = idx0 + (int64_t)k * kBlock;
+    const int64_t idx = idx0 + (int64_t)k * kWave;
       if constexpr (kScaled) {
         double acc = E + nbkg;
 #pragma unroll
@@ -1120,14 +1121,14 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     const int k1 = min(n_full, k0 + every);
     int k = k0;
     // reads of steps k + kPrefetch .. k + 2 kPrefetch - 1 from one pointer
-    GlobalCT nxt = cp + (int64_t)(k0 + kPrefetch) * kBlock;
-    for (; k + kPrefetch <= k1; k += kPrefetch, nxt += kPrefetch * kBlock) {  // uniform trip count
+    GlobalCT nxt = cp + (int64_t)(k0 + kPrefetch) * kWave;
+    for (; k + kPrefetch <= k1; k += kPrefetch, nxt += kPrefetch * kWave) {  // uniform trip count
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i) {
         const double d = (double)dq[i];  // widened (and looked up) first: the load can reuse its register
         const double iv = inv_of(dq[i], d);
         if constexpr (MODE != kModeModel) {
-          dq[i] = nxt[i * kBlock];
+          dq[i] = nxt[i * kWave];
           // keep the read here, a full kPrefetch steps before its use (the
           // scheduler would otherwise sink it towards the end of the loop)
           __builtin_amdgcn_sched_barrier(0);
@@ -1145,12 +1146,13 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   }
   if constexpr (MODE == kModeModel) return;
 
-  // workgroup reduction of the cost (compensated) and the gradient (fixed tree)
-  __shared__ Pair wred[kBlock / 64];
-  __shared__ double gred[kBlock / 64][kRS];
-  const int w = tid >> 6;
-  Pair pc = wave_pair_sum(Pair{lane_cost, 0.0});
-  if ((tid & 63) == 0) wred[w] = pc;
+  // wave reduction of the cost (compensated) and the gradient (fixed tree);
+  // lane 0 writes the segment's slot
+  const Pair pc = wave_pair_sum(Pair{lane_cost, 0.0});
+  if (lane == 0) {
+    slot[0] = pc.s;
+    slot[1] = pc.c;
+  }
   if constexpr (MODE == kModeGrad) {
 #pragma unroll
     for (int r = 0; r < kRS; ++r) {
@@ -1160,26 +1162,9 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         const int q = (r - kArg0) >> 1, kt = q / kMaxFT, f = q % kMaxFT, ai = (r - kArg0) & 1;
         used = kt < n_terms && f < Sh::nf(ts, kt) && ai < prim_nargs(Sh::prim(ts, kt, f));
       }
-      if (used && (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN)) {
-        const double s = wave_sum(g[r]);
-        if ((tid & 63) == 0) gred[w][r] = s;
-      } else if ((tid & 63) == 0) {
-        gred[w][r] = 0.0;
-      }
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    Pair t = wred[0];
-    for (int q = 1; q < kBlock / 64; ++q) t = pair_add(t, wred[q]);
-    slot[0] = t.s;
-    slot[1] = t.c;
-  }
-  if constexpr (MODE == kModeGrad) {
-    if (tid < kRS) {
-      double s = gred[0][tid];
-      for (int q = 1; q < kBlock / 64; ++q) s += gred[q][tid];
-      slot[2 + tid] = s;
+      double sr = 0.0;
+      if (used && (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN)) sr = wave_sum(g[r]);
+      if (lane == 0) slot[2 + r] = sr;
     }
   }
 }
@@ -1195,15 +1180,17 @@ __device__ __forceinline__ int histo_at(const DevHisto *hs, int n_histo, int64_t
   return lo;
 }
 
-// Tile launch: workgroup b evaluates tile b of its job.
+// The unit of work is one wave (64 lanes; four per workgroup, which share the
+// reciprocal table). Unit u is wave u % 4 of workgroup u / 4.
+// Tile launch: unit u evaluates tile u of its job.
 // Split launch (uniform jobs, split_w > 0): the n_vec x total (vector, bin)
-// space is cut into equal ranges of split_w bins, one per workgroup, so every
-// workgroup has the same work; a range is evaluated as the (vector, histogram)
-// segments it crosses. Segment (workgroup b, histogram j = v * n_histo + h)
-// owns slot b + j: the sum grows by one or two from one segment to the next,
-// so slots are unique and each histogram's slots are contiguous. When a range
-// starts exactly at a histogram start, slot b + j - 1 belongs to no segment
-// and is written as zero so that every slot inside a vector's span is defined.
+// space is cut into equal ranges of split_w bins, one per unit, so every unit
+// has the same work; a range is evaluated as the (vector, histogram) segments
+// it crosses. Segment (unit u, histogram j = v * n_histo + h) owns slot u + j:
+// the sum grows by one or two from one segment to the next, so slots are
+// unique and each histogram's slots are contiguous. When a range starts
+// exactly at a histogram start, slot u + j - 1 belongs to no segment and is
+// written as zero so that every slot inside a vector's span is defined.
 // Minimum waves per SIMD asked of the register allocator: the chi^2 cost
 // kernels of the compiled shapes fit six (80 registers) without spilling;
 // the others are left to the compiler's own choice.
@@ -1221,18 +1208,22 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
     for (int i = threadIdx.x; i < kInvTab; i += kBlock) inv_tab[i] = 1.0 / (double)(i > 0 ? i : 1);
     __syncthreads();
   }
+  // each wave is one unit of work; no workgroup barrier after this point
+  const int u = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + (int)(threadIdx.x / kWave));  // wave-uniform
+  const int lane = threadIdx.x & (kWave - 1);
+  if (u >= a.n_units) return;
   const bool split = a.split_w != 0;
   const int nh = a.tmpl.n_histo;
   int64_t pos = 0, end = 0;
   int v = 0, h = 0;
   if (split) {
-    pos = (int64_t)b * a.split_w;
+    pos = (int64_t)u * a.split_w;
     end = min(pos + a.split_w, (int64_t)a.n_vec * a.total);
     if (pos >= end) return;
     v = (int)(pos / a.total);
     h = histo_at(a.tmpl.histos, nh, pos - (int64_t)v * a.total);
     if (MODE != kModeModel && pos == (int64_t)v * a.total + a.tmpl.histos[h].off && (v > 0 || h > 0)) {
-      if (threadIdx.x < kSlot) a.partial[((int64_t)b + (int64_t)v * nh + h - 1) * kSlot + threadIdx.x] = 0.0;
+      if (lane < kSlot) a.partial[((int64_t)u + (int64_t)v * nh + h - 1) * kSlot + lane] = 0.0;
     }
   }
   for (;;) {
@@ -1242,8 +1233,8 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
     int64_t seg_end = 0;
     if (!split) {
       int job;
-      const DevJob J = job_of(a, b, job);
-      const DevTile T = J.tiles[b - J.block_base];
+      const DevJob J = job_of(a, u, job);
+      const DevTile T = J.tiles[u - J.unit_base];
       H = J.histos[T.histo];
       S.th = J.th;
       S.p = J.p;
@@ -1252,7 +1243,7 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
       S.begin = T.begin;
       S.n = T.n;
       // the job's slots are global across the per-shape launches of one batch
-      slot = a.partial + ((int64_t)J.tile_base + (b - J.block_base)) * kSlot;
+      slot = a.partial + ((int64_t)J.tile_base + (u - J.unit_base)) * kSlot;
     } else {
       H = uni(a.tmpl.histos[h]);
       const int64_t h_start = (int64_t)v * a.total + H.off;
@@ -1263,7 +1254,7 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
       S.model_out = a.tmpl.model_out;
       S.begin = pos - h_start;
       S.n = (int32_t)(seg_end - pos);
-      slot = a.partial + ((int64_t)b + (int64_t)v * nh + h) * kSlot;
+      slot = a.partial + ((int64_t)u + (int64_t)v * nh + h) * kSlot;
     }
     S.off = H.off;
     S.first = H.first;
@@ -1280,7 +1271,6 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
       h = 0;
       ++v;
     }
-    __syncthreads();  // the next segment reuses the reduction buffers
   }
 }
 
@@ -1320,7 +1310,7 @@ __global__ __launch_bounds__(kBlock) void merge2_kernel(LaunchArgs first, int n_
 
 template <int COST, int MODE, typename Sh>
 hipError_t launch_shape(const LaunchArgs &a, int count_f64, hipStream_t s) {
-  dim3 grid(a.n_blocks), block(kBlock);
+  dim3 grid((a.n_units + kBlock / kWave - 1) / (kBlock / kWave)), block(kBlock);  // n_units counts units (waves)
   if (count_f64)
     hipLaunchKernelGGL((eval_kernel<COST, MODE, double, ShapeGeneric>), grid, block, 0, s, a);
   else
@@ -1398,7 +1388,7 @@ hipError_t launch_typed(const LaunchArgs &a, int count_f64, int shape, hipStream
 }  // namespace
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s) {
-  if (a.n_blocks <= 0) return hipSuccess;
+  if (a.n_units <= 0) return hipSuccess;
   if (a.anchor_every < 1 || a.anchor_every > 256) return hipErrorInvalidValue;
   if (mode == kModeModel) return launch_typed<MU_COST_CHI2, kModeModel>(a, count_f64, shape, s);
   if (a.cost_kind == MU_COST_CHI2)

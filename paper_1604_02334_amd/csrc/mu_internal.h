@@ -28,6 +28,7 @@ constexpr int kFunStage = 32;
 // Partial slot of one tile: cost (s, c) then kRS gradient components.
 constexpr int kSlot = 2 + kRS;  // 32 doubles
 constexpr int kBlock = 256;     // threads per evaluation workgroup
+constexpr int kWave = 64;       // lanes per wave: the unit of work of an evaluation launch
 constexpr int kRefNone = -1;
 
 constexpr __host__ __device__ int arg_index(int k, int i, int a) { return kArg0 + (k * kMaxFT + i) * 2 + a; }
@@ -81,7 +82,7 @@ struct DevJob {
   int32_t n_tiles;
   int32_t n_histo;
   int32_t tile_base;     // first partial slot of this job
-  int32_t block_base;    // first workgroup of this job in its launch
+  int32_t unit_base;     // first work unit (wave) of this job in its launch
 };
 
 enum Mode : int { kModeCost = 0, kModeGrad = 1, kModeModel = 2 };
@@ -98,20 +99,22 @@ enum Shape : int {
 };
 
 struct LaunchArgs {
+  // The unit of work is one wave of kWave lanes; a workgroup holds
+  // kBlock / kWave units.
   // Uniform launch (jobs == null): job v is `tmpl` with its parameter vector
-  // and outputs advanced by v strides, and owns workgroups
+  // and outputs advanced by v strides, and owns units
   // [v * tmpl.n_tiles, (v + 1) * tmpl.n_tiles).
   DevJob tmpl;
   int64_t p_stride, grad_stride, histo_stride;
-  // Mapped launch: explicit jobs and a workgroup -> job table.
+  // Mapped launch: explicit jobs and a unit -> job table.
   const DevJob *jobs;
-  const int32_t *block_job;
-  int32_t n_blocks;
+  const int32_t *unit_job;
+  int32_t n_units;
   int32_t cost_kind;
   int32_t anchor_every;  // lane steps between exact re-evaluations, 1..256
   // Split launch (jobs == null, split_w > 0): n_vec vectors of `total`
-  // fit-range bins each, cut into ranges of split_w bins, one per workgroup;
-  // slot b + v * n_histo + h of `partial` belongs to workgroup b's segment of
+  // fit-range bins each, cut into ranges of split_w bins, one per unit;
+  // slot u + v * n_histo + h of `partial` belongs to unit u's segment of
   // histogram h of vector v.
   int32_t n_vec;
   int64_t split_w;
@@ -120,7 +123,8 @@ struct LaunchArgs {
 };
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);
-// Workgroups of the evaluation kernel resident per compute unit (0 if unknown).
+// Workgroups (of kBlock / kWave units each) of the evaluation kernel resident
+// per compute unit (0 if unknown).
 int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape);
 // Merge the tile slots of jobs [0, n_jobs) of `a` (uniform or mapped).
 hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s);

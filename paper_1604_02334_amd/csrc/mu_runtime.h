@@ -14,7 +14,7 @@ struct mu_ctx;
 namespace mu {
 
 constexpr int kMinTile = 1024, kMaxTile = 65536;
-constexpr int kMaxSplit = 1 << 26;  // largest explicit bins-per-workgroup value
+constexpr int kMaxSplit = 1 << 26;  // largest explicit bins-per-unit value
 constexpr int kDefaultAnchor = 64;
 
 // Grow-only device buffer owned by a context.
@@ -46,7 +46,7 @@ mu_status eval_dev(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, 
 struct TileSet;
 mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
                     const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
-                    double *cost, double *grad, int64_t n_blocks, int anchor);
+                    double *cost, double *grad, int64_t n_units, int anchor);
 
 }  // namespace mu
 
@@ -65,7 +65,7 @@ struct mu_ctx {
   };
   std::vector<Tuned> tuned;
   int pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const;
-  // Bins per workgroup of a split launch (single dataset, n_vec vectors).
+  // Bins per wave of a split launch (single dataset, n_vec vectors).
   int64_t pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const;
   int specialize = 1;  // use the compiled shape kernels when a theory matches one
   hipEvent_t staging_free = nullptr;  // recorded after each upload from `staging`

@@ -35,6 +35,23 @@ def _mk(ctx, theory, histos, counts):
     return api.Theory(ctx, theory), api.Data(ctx, histos, counts)
 
 
+def _rounding_bound(theory, histos, counts, p, kind="chi2", ulps=256):
+    """Largest cost difference expected between two evaluations whose expected
+    counts N_n each carry up to `ulps` units of rounding (2^-53) of relative
+    error, e.g. the cost pass, which folds N0, the lifetime and the term
+    weights into its recurrence states, against the gradient pass, which keeps
+    them apart. To first order the cost (Eq. 2 or 3) moves by
+    sum_n |d term / d N| |N_n| ulps 2^-53; near the minimum |d term / d N| N is
+    about 2 sqrt(N) per bin, so the relative bound is far above 2^-53. Anchors
+    every 64 lane steps bound the recurrences' own drift well inside 256 ulps."""
+    s = 0.0
+    for h, c in zip(histos, counts):
+        N = model.model(theory, h, p)
+        d = np.asarray(c, dtype=np.float64)[h["first"]:h["last"] + 1]
+        s += float(np.sum(np.abs(model.cost_dN(d, N, kind) * N)))
+    return ulps * 2.0 ** -53 * s
+
+
 @pytest.mark.parametrize("kind", ["chi2", "poisson"])
 def test_c1_cost_parity(ctx, kind):
     _say("c1 cost", kind)
@@ -129,14 +146,16 @@ def test_c3_vectors_sampled(ctx):
     cg, gg = api.chi2_grad(ctx, d, th, P)
     # the cost pass folds N0, the lifetime and the term weights into its
     # recurrence states, the gradient pass keeps them apart: equal to rounding
-    assert np.all(np.abs(cg - got) <= 1e-14 * np.abs(got))
+    bound = np.array([_rounding_bound(cfg["theory"], cfg["histos"], counts, q) for q in P])
+    assert np.all(np.abs(cg - got) <= bound)
     idx = np.random.default_rng(0).choice(P.shape[0], 48, replace=False)
     for v in idx:
         ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v])
         assert abs(got[v] - ref) <= REL * ref
-        # a separate launch may pick another tile size: equal to rounding
+        # a separate launch may pick another tile size (other anchor
+        # positions): equal to rounding
         one = api.chi2_eval(ctx, d, th, P[v])
-        assert abs(one[0] - got[v]) <= 1e-13 * got[v]
+        assert abs(one[0] - got[v]) <= bound[v]
     # at one fixed tile size the batched and separate launches are bitwise equal
     try:
         ctx.tile = 4096
@@ -266,16 +285,18 @@ def test_batch_uneven_datasets(ctx):
     for kind in ("chi2", "poisson"):
         c, g = api.chi2_batch(ctx, ds, ths, P, kind, grad=True)
         c_only = api.chi2_batch(ctx, ds, ths, P, kind)
-        assert np.all(np.abs(c - c_only) <= 1e-14 * np.abs(c_only))
         for j, s in enumerate(sets):
             n = s["start"].size
+            # gradient pass against the (scaled-state) cost pass: to rounding
+            bound = _rounding_bound(s["theory"], s["histos"], cnts[j], s["start"], kind)
+            assert abs(c[j] - c_only[j]) <= bound, (j, c[j] - c_only[j], bound)
             ref = model.cost(s["theory"], s["histos"], cnts[j], s["start"], kind)
             assert abs(c[j] - ref) <= REL * ref, (j, s["family"])
             refg = model.grad(s["theory"], s["histos"], cnts[j], s["start"], kind)
             scale = model.grad_abs_scale(s["theory"], s["histos"], cnts[j], s["start"], kind)
             assert np.all(np.abs(g[j, :n] - refg) <= REL * scale), (j, s["family"])
             one = api.chi2_eval(ctx, ds[j], ths[j], s["start"], kind)
-            assert abs(one[0] - c[j]) <= 1e-13 * c[j]
+            assert abs(one[0] - c_only[j]) <= bound
 
 
 def test_torch_device_path_and_autograd(ctx):
@@ -296,7 +317,7 @@ def test_torch_device_path_and_autograd(ctx):
     host_c, _ = api.chi2_grad(ctx, d, th, p.detach().cpu().numpy())
     assert c.item() == host_c[0]
     host = api.chi2_eval(ctx, d, th, p.detach().cpu().numpy())
-    assert abs(c.item() - host[0]) <= 1e-14 * host[0]
+    assert abs(c.item() - host[0]) <= _rounding_bound(cfg["theory"], cfg["histos"], counts, p.detach().cpu().numpy())
 
 
 def test_specialised_kernels_match_generic_and_direct(ctx):
@@ -345,8 +366,8 @@ def test_autotune_choice_keeps_parity(ctx):
     th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
     P = np.stack([perturbed(cfg["p_true"], 1e-3, 30 + v) for v in range(64)])
     tile, anchor, us = api.autotune(ctx, d, th, P)
-    # bins per workgroup: a power of two or a whole-round split, at least one bin per lane
-    assert tile >= 256 and anchor in (32, 64, 128, 256) and us > 0
+    # bins per wave: a power of two or a whole-round split, at least one bin per lane
+    assert tile >= 64 and anchor in (32, 64, 128, 256) and us > 0
     got = api.chi2_eval(ctx, d, th, P)
     for v in (0, 17, 63):
         ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v])
@@ -421,10 +442,10 @@ def _stencil(p, rel=1e-4):
 
 def test_bench_launch_configuration_sampled(ctx):
     """The launch the benchmark times: C2 (16 x 65536 bins), the 104-vector
-    central-difference stencil at 65536 bins per workgroup and anchors every
-    256 steps, plus the gradient at the centre in the same call. Sampled
-    stencil vectors against the oracle one by one, every vector against the
-    default launch shape to rounding."""
+    central-difference stencil plus the gradient at the centre in the same
+    call, with the launch shapes the autotuner picks for both (as the
+    benchmark does). Sampled stencil vectors against the oracle one by one,
+    every vector against the default launch shape to rounding."""
     _say("bench launch configuration")
     cfg, counts = c2()
     th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
@@ -432,11 +453,9 @@ def test_bench_launch_configuration_sampled(ctx):
     S = _stencil(p0)
     assert S.shape == (104, 52)
     default = api.chi2_eval(ctx, d, th, S)
-    try:
-        ctx.tile, ctx.anchor = 65536, 256
-        cg, g, cc = api.chi2_eval_grad(ctx, d, th, p0, S)
-    finally:
-        ctx.tile, ctx.anchor = 0, 0
+    api.autotune(ctx, d, th, S)
+    api.autotune(ctx, d, th, p0[None, :], grad=True)
+    cg, g, cc = api.chi2_eval_grad(ctx, d, th, p0, S)
     assert np.all(np.abs(cc - default) <= 1e-13 * default)
     for v in (0, 37, 88, 103):
         ref = model.cost(cfg["theory"], cfg["histos"], counts, S[v])
@@ -448,8 +467,8 @@ def test_bench_launch_configuration_sampled(ctx):
 
 
 def test_split_ranges_cross_histogram_and_vector_boundaries(ctx):
-    """Uneven fit ranges and bins-per-workgroup values that divide nothing:
-    workgroup ranges start inside histograms, cover several histograms and
+    """Uneven fit ranges and bins-per-wave values that divide nothing: wave
+    ranges start inside histograms, cover several histograms and
     cross from one vector to the next; costs, per-histogram costs and
     gradients of every vector against the oracle."""
     _say("split ranges")
@@ -466,7 +485,7 @@ def test_split_ranges_cross_histogram_and_vector_boundaries(ctx):
     ref_g = [model.grad(th_d, hs, counts, P[v]) for v in range(7)]
     scales = [model.grad_abs_scale(th_d, hs, counts, P[v]) for v in range(7)]
     try:
-        for W in (256, 300, 777, 1000, 5000, 18122, 20000, 100000):
+        for W in (64, 100, 256, 300, 777, 1000, 5000, 18122, 20000, 100000):
             ctx.tile = W
             c, ph = api.chi2_eval(ctx, d, th, P, per_histo=True)
             cg, g = api.chi2_grad(ctx, d, th, P)
@@ -480,7 +499,7 @@ def test_split_ranges_cross_histogram_and_vector_boundaries(ctx):
 
 
 def test_reciprocal_table_boundary_counts(ctx):
-    """Integer counts around the size of the per-workgroup reciprocal table
+    """Integer counts around the size of the reciprocal table
     (2048) and far above it, interleaved so that one wave mixes table reads
     with the hardware-reciprocal path; zeros take v = 1."""
     _say("reciprocal table boundary")

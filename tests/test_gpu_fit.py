@@ -73,7 +73,11 @@ def test_batched_and_plain_paths_agree(ctx):
     """Uneven independent datasets: the batched path (one launch per round,
     analytic gradients) and the plain path (one launch per cost evaluation,
     central differences) reach the same minimum; the plain one needs many
-    more evaluations."""
+    more evaluations. A set whose covariance is degenerate (correlation
+    matrix condition number above 1e6: some parameter combination is not
+    determined by the data) has no well-defined minimum point, only a
+    well-defined minimum cost; there the two costs agree to 1e-2 (a hundredth
+    of the change of 1 that marks one standard deviation)."""
     _say("batched vs plain")
     cfg = synth.config_c4(n_sets=12, lo_exp=11, hi_exp=13)
     rng = cfg["rng"]
@@ -91,6 +95,10 @@ def test_batched_and_plain_paths_agree(ctx):
         n = s["start"].size
         sig = np.sqrt(np.abs(np.diag(covb[j]))[:n])
         if rb[j]["status"] != 0 or rp[j]["status"] != 0:
+            continue
+        corr = covb[j][:n, :n] / np.outer(sig, sig)
+        if np.linalg.cond(corr) > 1e6:
+            assert abs(rb[j]["cost"] - rp[j]["cost"]) <= 1e-2, (j, s["family"], rb[j], rp[j])
             continue
         ok, worst = _agree(pb[j, :n], pp[j, :n], sig, tol=1e-5)
         assert ok, (j, s["family"], worst)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -379,7 +380,78 @@ mu_status mu_data::tiles(int tile_bins, const TileSet **out) {
   return MU_OK;
 }
 
+// The gradient merge plan of (th, this dataset); layout next to kPlanHead.
+mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out) {
+  for (const Plan &p : plans)
+    if (p.theory_id == th->id) {
+      *out = p.d;
+      return MU_OK;
+    }
+  const DevTheory &T = th->h;
+  std::vector<int> act;
+  for (int r = 0; r < kRS; ++r)
+    if (T.rref[r].kind == MU_REF_PAR || T.rref[r].kind == MU_REF_FUN) act.push_back(r);
+  const int na = (int)act.size(), n_par = T.n_par;
+  const int n_chunks = (n_histo + kMergeChunk - 1) / kMergeChunk;
+  std::vector<std::vector<int32_t>> blocks(n_chunks);
+  size_t stride = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const int h0 = c * kMergeChunk, nh = std::min(kMergeChunk, n_histo - h0);
+    // target of each entry e = q * na + i: parameter m, or function m
+    std::vector<int32_t> koff(n_par + 1, 0), dest(nh * na), fi;
+    std::vector<int> par(nh * na, -1);
+    for (int q = 0; q < nh; ++q)
+      for (int i = 0; i < na; ++i) {
+        const DevRef &ref = T.rref[act[i]];
+        const int m = th->map[(size_t)hh[h0 + q].map_row * T.n_slots + ref.slot];
+        const int e = q * na + i;
+        if (ref.kind == MU_REF_PAR) {
+          par[e] = m;
+          koff[m + 1]++;
+        } else {
+          dest[e] = -1 - (int32_t)fi.size();
+          fi.push_back(m);
+        }
+      }
+    for (int k = 0; k < n_par; ++k) koff[k + 1] += koff[k];
+    std::vector<int32_t> fill(koff.begin(), koff.end() - 1);
+    for (int e = 0; e < nh * na; ++e)
+      if (par[e] >= 0) dest[e] = fill[par[e]]++;
+    std::vector<int32_t> &b = blocks[c];
+    b.push_back(koff[n_par]);
+    b.push_back((int32_t)fi.size());
+    b.insert(b.end(), koff.begin(), koff.end());
+    b.insert(b.end(), dest.begin(), dest.end());
+    b.insert(b.end(), fi.begin(), fi.end());
+    stride = std::max(stride, b.size());
+  }
+  stride = (stride + 63) / 64 * 64;
+  if (stride > (size_t)kPlanBlockMax) {  // cannot happen: nh * n_act + n_fe <= 2 kMergeChunk kRS
+    set_err(ctx, "gradient merge plan block of %zu entries", stride);
+    return MU_E_UNSUPPORTED;
+  }
+  std::vector<int32_t> buf(kPlanHead + (size_t)n_chunks * stride, 0);
+  buf[0] = na;
+  buf[1] = n_par;
+  buf[2] = (int32_t)stride;
+  for (int i = 0; i < na; ++i) buf[kPlanAct + i] = act[i];
+  for (int c = 0; c < n_chunks; ++c) std::copy(blocks[c].begin(), blocks[c].end(), buf.begin() + kPlanHead + c * stride);
+  Plan p{th->id, nullptr};
+  hipError_t e = hipMalloc(&p.d, buf.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpy(p.d, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (p.d) hipFree(p.d);
+    return hip_fail(ctx, e, "gradient merge plan");
+  }
+  plans.push_back(p);
+  *out = p.d;
+  return MU_OK;
+}
+
 void mu_data::free_dev() {
+  for (Plan &p : plans)
+    if (p.d) hipFree(p.d);
+  plans.clear();
   if (counts) hipFree(counts);
   counts = nullptr;
   if (d_hh) hipFree(d_hh);
@@ -688,8 +760,10 @@ extern "C" mu_status mu_theory_create(mu_ctx *ctx, const mu_theory_desc *d, mu_t
     return s;
   }
   hipSetDevice(ctx->device);
+  static std::atomic<uint64_t> next_id{1};
   mu_theory *th = new mu_theory();
   th->ctx = ctx;
+  th->id = next_id++;
   DevTheory &h = th->h;
   std::memset(&h, 0, sizeof h);
   h.tau_mu = d->tau_mu;
@@ -842,9 +916,12 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
     const size_t n_slots = (size_t)n_units + (size_t)n_vec * d->n_histo;
     if ((st = partial.ensure(ctx, n_slots * kSlot * sizeof(double), false)) != MU_OK) return st;
   }
+  const int32_t *plan = nullptr;
+  if (mode == kModeGrad && (st = d->grad_plan(th, &plan)) != MU_OK) return st;
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.tmpl.th = th->d_th;
+  a.tmpl.plan = plan;
   a.tmpl.histos = d->d_hh;
   a.tmpl.counts = d->counts;
   a.tmpl.tiles = nullptr;
@@ -1164,6 +1241,8 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     J.histo_out = nullptr;
     J.grad_out = dg ? dg + (size_t)j * ld : nullptr;
     J.model_out = nullptr;
+    J.plan = nullptr;
+    if (grad && (st = const_cast<mu_data *>(data[j])->grad_plan(th[j], &J.plan)) != MU_OK) return st;
     J.n_tiles = sets[j]->n_tiles;
     J.n_histo = data[j]->n_histo;
     J.tile_base = slot_base;

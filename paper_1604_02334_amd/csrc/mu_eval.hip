@@ -452,25 +452,32 @@ __device__ __forceinline__ DevJob job_of(const LaunchArgs &a, int b, int &job) {
 
 // ------------------------------------------------------------ merge kernel
 
-// Compensated sum of slot component `c` over tiles [k0, k1): eight independent
-// loads in flight, lanes of the eight-wide stripe combined in a fixed order.
-__device__ double sum_slots(const double *P, int k0, int k1, int c) {
-  Pair acc[8];
+// Compensated sum of slot component `c` over tiles k0, k0 + step, ... < k1:
+// kU independent loads in flight, lanes of the kU-wide stripe combined in a
+// fixed order.
+__device__ Pair sum_slots(const double *P, int k0, int k1, int step, int c) {
+  constexpr int kU = 8;
+  Pair acc[kU];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = Pair{0.0, 0.0};
+  for (int u = 0; u < kU; ++u) acc[u] = Pair{0.0, 0.0};
   int k = k0;
-  for (; k + 8 <= k1; k += 8) {
-    double v[8];
+  for (; k + (kU - 1) * step < k1; k += kU * step) {
+    double v[kU];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)(k + u) * kSlot + c];
+    for (int u = 0; u < kU; ++u) v[u] = P[(int64_t)(k + u * step) * kSlot + c];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = pair_add(acc[u], Pair{v[u], 0.0});
+    for (int u = 0; u < kU; ++u) acc[u] = pair_add(acc[u], Pair{v[u], 0.0});
   }
-  for (int u = 0; k < k1; ++k, ++u) acc[u] = pair_add(acc[u], Pair{P[(int64_t)k * kSlot + c], 0.0});
+  // the rest (fewer than kU): loads first, then the sums
+  double v[kU - 1];
+#pragma unroll
+  for (int u = 0; u < kU - 1; ++u) v[u] = k + u * step < k1 ? P[(int64_t)(k + u * step) * kSlot + c] : 0.0;
+#pragma unroll
+  for (int u = 0; u < kU - 1; ++u) acc[u] = pair_add(acc[u], Pair{v[u], 0.0});
   Pair t = acc[0];
 #pragma unroll
-  for (int u = 1; u < 8; ++u) t = pair_add(t, acc[u]);
-  return pair_value(t);
+  for (int u = 1; u < kU; ++u) t = pair_add(t, acc[u]);
+  return t;
 }
 
 // Same for the cost pairs (s, c) of tiles [k0, k1).
@@ -527,15 +534,15 @@ struct SlotMap {
 template <int MODE>
 __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   // Phase A issues every load that depends on nothing else (the slot span,
-  // the theory's resolved-scalar descriptors, the first chunk's histogram
-  // records); phase B issues the cost slots and the first chunk's gradient
-  // entries together. Later histogram chunks (more than HC histograms) add
-  // two rounds each.
-  constexpr int HC = 32;  // histograms per chunk
+  // the plan's header and active scalars, the first chunk's histogram
+  // records); phase B issues the cost slots, the first chunk's gradient slots
+  // and its plan block together. Later histogram chunks add two rounds each.
+  constexpr int HC = kMergeChunk;
   constexpr int kWaves = kBlock / 64;
+  constexpr bool G = MODE == kModeGrad;
   __shared__ Pair red[kWaves];
   __shared__ int span_s[2];
-  __shared__ int rk0[HC], rk1[HC], rrow[HC];
+  __shared__ int rk0[HC], rk1[HC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   SlotMap sm;
   sm.J = &J;
@@ -545,22 +552,21 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   sm.jbase = job * J.n_histo;
   const double *P = sm.P;
   const DevTheory *th = J.th;
-  const int n_par = MODE == kModeGrad ? th->n_par : 0;
-  const bool need_chunks = MODE == kModeGrad || J.histo_out != nullptr;
+  const int n_par = G ? th->n_par : 0;
+  const bool need_chunks = G || J.histo_out != nullptr;
 
   // chain rule through the map / function array (gradient mode):
   //   g_k = sum_h sum_r gR[h][r] dR_r/dp_k, each gR[h][r] a sum over h's slots.
-  // Only the scalars the theory takes from p or f are kept (list `act`). For a
-  // chunk of histograms the entries e = (hh, i) hold gR and the map lookup
-  // (pidx >= 0: parameter index; <= -2: function -(2 + i); -1: none) in LDS;
-  // then one wave per parameter gathers its entries, lane-strided, and
-  // combines them with a fixed-shape tree, so the order never depends on timing.
-  __shared__ double gR[MODE == kModeGrad ? HC * kRS : 1];
-  __shared__ int pidx[MODE == kModeGrad ? HC * kRS : 1];
-  __shared__ int act[kRS], act_slot[kRS], act_fun[kRS];
-  __shared__ int n_act_s;
-  __shared__ double acc_s[MODE == kModeGrad ? MU_MAX_PAR : 1];
-  __shared__ double acc_c[MODE == kModeGrad ? MU_MAX_PAR : 1];
+  // Per chunk of histograms the plan gives each entry e = (hh, i) its place:
+  // in parameter k's contiguous run of srt (runs in koff, entries in entry
+  // order within a run), or in the list of function entries fsrt (entry
+  // order). Each parameter then sums its run and the function entries in that
+  // fixed order, whatever the timing.
+  __shared__ double srt[G ? HC * kRS : 1], fsrt[G ? HC * kRS : 1];
+  __shared__ int pl[G ? kPlanBlockMax : 1];
+  __shared__ int act[kRS], hdr[3];
+  __shared__ double acc_s[G ? MU_MAX_PAR : 1];
+  __shared__ double acc_c[G ? MU_MAX_PAR : 1];
 
   auto stage_ranges = [&](int h0) {
     const int nh = min(HC, J.n_histo - h0);
@@ -569,98 +575,51 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
       sm.range(h0 + hh, k0, k1);
       rk0[hh] = k0;
       rk1[hh] = k1;
-      rrow[hh] = J.histos[h0 + hh].map_row;
     }
   };
-  // gradient entries and per-histogram costs of the staged chunk
+  // per-histogram costs, the chunk's plan block and its gradient entries
   auto chunk_entries = [&](int h0) {
     const int nh = min(HC, J.n_histo - h0);
     if (J.histo_out)
       for (int hh = tid; hh < nh; hh += kBlock) J.histo_out[h0 + hh] = sum_slot_pairs(P, rk0[hh], rk1[hh]);
-    if constexpr (MODE == kModeGrad) {
-      const int na = n_act_s;
-      for (int e = tid; e < nh * na; e += kBlock) {
-        const int hh = e / na, i = e - hh * na;
-        const int m = th->map[rrow[hh] * th->n_slots + act_slot[i]];
-        gR[e] = sum_slots(P, rk0[hh], rk1[hh], 2 + act[i]);
-        pidx[e] = act_fun[i] ? -(2 + m) : m;
+    if constexpr (G) {
+      const int na = hdr[0], stride = hdr[2];
+      const int32_t *blk = J.plan + kPlanHead + (int64_t)(h0 / HC) * stride;
+      for (int q = tid; q < stride; q += kBlock) pl[q] = blk[q];
+      const int32_t *dst = blk + 3 + n_par;
+      // S adjacent lanes per entry (up to 8, while the entries fill the
+      // workgroup) take its slots in turn; a fixed butterfly combines them
+      const int ne = nh * na;
+      int S = 1;
+      while (S < 8 && ne * S * 2 <= kBlock) S <<= 1;
+      for (int base = 0; base < ne * S; base += kBlock) {  // uniform: every lane reaches the shuffles
+        const int t = base + tid, e = t / S, sl = t % S;
+        const bool on = t < ne * S;
+        Pair v{0.0, 0.0};
+        int at = 0;
+        if (on) {
+          const int hh = e / na, i = e - hh * na;
+          at = dst[e];
+          v = sum_slots(P, rk0[hh] + sl, rk1[hh], S, 2 + act[i]);
+        }
+        for (int o = 1; o < S; o <<= 1) v = pair_add(v, Pair{__shfl_xor(v.s, o, 64), __shfl_xor(v.c, o, 64)});
+        if (on && sl == 0) {
+          if (at >= 0)
+            srt[at] = pair_value(v);
+          else
+            fsrt[-1 - at] = pair_value(v);
+        }
       }
     }
   };
-  // Per parameter, its entries of the staged chunk in a fixed order: a
-  // counting sort by parameter (counts, exclusive scan, then each entry's
-  // rank among the earlier entries of its parameter), after which thread k
-  // sums its own contiguous run, then the function entries in entry order.
-  __shared__ int koff[MODE == kModeGrad ? MU_MAX_PAR + 1 : 1];
-  __shared__ double srt[MODE == kModeGrad ? HC * kRS : 1];
-  __shared__ int fun_e[MODE == kModeGrad ? HC * kRS : 1];
-  __shared__ int n_fun_s;
   auto chunk_gather = [&](int h0) {
-    if constexpr (MODE == kModeGrad) {
-      const int ne = min(HC, J.n_histo - h0) * n_act_s;
-      for (int k = tid; k <= n_par; k += kBlock) koff[k] = 0;
-      if (tid == 0) n_fun_s = 0;
-      __syncthreads();
-      for (int e = tid; e < ne; e += kBlock) {
-        const int pi = pidx[e];
-        if (pi >= 0) atomicAdd(&koff[pi + 1], 1);  // counts only: the order of the adds does not matter
-      }
-      __syncthreads();
-      if (wave == 0) {
-        // inclusive scan of koff[1 .. n_par]: lane l owns a run of `per` values
-        const int per = (n_par + 63) / 64;
-        int run = 0;
-        for (int q = 0; q < per; ++q) {
-          const int k = lane * per + q + 1;
-          if (k <= n_par) run += koff[k];
-        }
-        int incl = run;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int v = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += v;
-        }
-        int base = incl - run;
-        for (int q = 0; q < per; ++q) {
-          const int k = lane * per + q + 1;
-          if (k <= n_par) {
-            base += koff[k];
-            koff[k] = base;
-          }
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < ne; e += kBlock) {
-        const int pi = pidx[e];
-        if (pi == -1) continue;
-        // rank among the earlier entries of the same parameter (or among the
-        // earlier function entries): eight independent reads per step
-        const bool fun = pi <= -2;
-        int rank = 0, e2 = 0;
-        for (; e2 + 8 <= e; e2 += 8) {
-          int v[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = pidx[e2 + u];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) rank += fun ? (v[u] <= -2) : (v[u] == pi);
-        }
-        for (; e2 < e; ++e2) rank += fun ? (pidx[e2] <= -2) : (pidx[e2] == pi);
-        if (fun) {
-          fun_e[rank] = e;
-          atomicAdd(&n_fun_s, 1);
-        } else {
-          srt[koff[pi] + rank] = gR[e];
-        }
-      }
-      __syncthreads();
-      const int nf = n_fun_s;
+    if constexpr (G) {
+      const int ne = min(HC, J.n_histo - h0) * hdr[0], n_fe = pl[1];
+      const int *koff = pl + 2, *fi = pl + 3 + n_par + ne;
       for (int k = tid; k < n_par; k += kBlock) {
         Pair q{acc_s[k], acc_c[k]};
         for (int j = koff[k]; j < koff[k + 1]; ++j) q = pair_add(q, Pair{srt[j], 0.0});
-        for (int f = 0; f < nf; ++f) {
-          const int e = fun_e[f];
-          q = pair_add(q, Pair{gR[e] * th->F[(int64_t)(-2 - pidx[e]) * n_par + k], 0.0});
-        }
+        for (int f = 0; f < n_fe; ++f) q = pair_add(q, Pair{fsrt[f] * th->F[(int64_t)fi[f] * n_par + k], 0.0});
         acc_s[k] = q.s;
         acc_c[k] = q.c;
       }
@@ -678,22 +637,9 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
     sm.range(J.n_histo - 1, k0, k1);
     span_s[1] = k1;
   }
-  if constexpr (MODE == kModeGrad) {
-    if (wave == 0) {
-      // compaction in order of r: lane r keeps its scalar at the rank of r
-      // among the active ones
-      DevRef ref{};
-      if (lane < kRS) ref = th->rref[lane];
-      const bool on = lane < kRS && (ref.kind == MU_REF_PAR || ref.kind == MU_REF_FUN);
-      const unsigned long long mask = __ballot(on);
-      if (on) {
-        const int at = __popcll(mask & ((1ull << lane) - 1ull));
-        act[at] = lane;
-        act_slot[at] = ref.slot;
-        act_fun[at] = ref.kind == MU_REF_FUN;
-      }
-      if (lane == 0) n_act_s = __popcll(mask);
-    }
+  if constexpr (G) {
+    if (tid >= 128 && tid < 128 + kRS) act[tid - 128] = J.plan[kPlanAct + tid - 128];
+    if (tid >= 192 && tid < 195) hdr[tid - 192] = J.plan[tid - 192];
     for (int k = tid; k < n_par; k += kBlock) {
       acc_s[k] = 0.0;
       acc_c[k] = 0.0;
@@ -726,7 +672,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
     __syncthreads();
     chunk_gather(h0);
   }
-  if constexpr (MODE == kModeGrad) {
+  if constexpr (G) {
     __syncthreads();
     for (int k = tid; k < n_par; k += kBlock) J.grad_out[k] = pair_value(Pair{acc_s[k], acc_c[k]});
   }

@@ -31,6 +31,24 @@ constexpr int kBlock = 256;     // threads per evaluation workgroup
 constexpr int kWave = 64;       // lanes per wave: the unit of work of an evaluation launch
 constexpr int kRefNone = -1;
 
+// Gradient merge plan of one (theory, dataset) pair, int32, built on the host.
+// The merge forms, per histogram h and active resolved scalar r (one whose
+// reference is a parameter or a function value), the entry gR = sum over h's
+// slots of dcost/dR_r, and adds it to the parameter (or, times F[i][k], to
+// every parameter k of function i) that the map assigns to r in h's row.
+// Layout: [0] n_act, [1] n_par, [2] block stride, act[kRS] at kPlanAct (the
+// active scalars r, ascending); then per chunk c of kMergeChunk histograms a
+// block at kPlanHead + c * stride: n_pe, n_fe, koff[n_par + 1] (parameter k's
+// entries occupy positions koff[k] .. koff[k + 1] - 1 of the sorted list),
+// dest[nh * n_act] (for entry e = hh * n_act + i: its position in the sorted
+// list, entries of one parameter in entry order; or -1 - j for the j-th entry,
+// in entry order, that feeds a function) and fi[n_fe] (the function of each
+// function entry).
+constexpr int kMergeChunk = 32;  // histograms per merge chunk
+constexpr int kPlanAct = 4;
+constexpr int kPlanHead = 64;
+constexpr int kPlanBlockMax = (3 + MU_MAX_PAR + 2 * kMergeChunk * kRS + 63) / 64 * 64;
+
 constexpr __host__ __device__ int arg_index(int k, int i, int a) { return kArg0 + (k * kMaxFT + i) * 2 + a; }
 
 struct DevRef {
@@ -79,6 +97,7 @@ struct DevJob {
   double *histo_out;     // [n_histo] or null
   double *grad_out;      // [n_par] or null
   double *model_out;     // per-bin N (model evaluation) or null
+  const int32_t *plan;   // gradient merge plan (gradient launches) or null
   int32_t n_tiles;
   int32_t n_histo;
   int32_t tile_base;     // first partial slot of this job

@@ -118,11 +118,20 @@ struct mu_data {
   mu::DevHisto *d_hh = nullptr;  // device copy of hh (split launches)
   // Tables for `tile_bins`, built on first use and kept until destruction.
   mu_status tiles(int tile_bins, const mu::TileSet **out);
+  // Gradient merge plans, one per theory used with this dataset (by theory
+  // id), built on first use and kept until destruction.
+  struct Plan {
+    uint64_t theory_id;
+    int32_t *d;
+  };
+  std::vector<Plan> plans;
+  mu_status grad_plan(const mu_theory *th, const int32_t **out);
   void free_dev();
 };
 
 struct mu_theory {
   mu_ctx *ctx = nullptr;
+  uint64_t id = 0;  // unique per process (never reused, unlike the address)
   mu::DevTheory h;
   int shape = 0;  // mu::Shape of the program
   std::vector<int32_t> map;

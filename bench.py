@@ -42,16 +42,17 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # lane-operations per second (one instruction per lane, FMA counted once).
 PEAK_FP64_TOPS = 39.3
 # Per bin of the 16-detector cost pass as the kernel computes it (lifetime,
-# N0 and term weights folded into the first factor of each term; reciprocal
+# N0 and term weights folded into the first factor of each term, the
+# exponential of the se * tf term into its complex rotation state; reciprocal
 # variance from the workgroup's table):
-#   model: lifetime 1 mul, exponential 1 mul, rotation 2 mul + 2 fma, Gaussian
-#   2 mul, sigma t 1 add, 1 - (sigma t)^2 1 fma, background 1 add, two term
-#   accumulations 2 fma                       -> 13 instructions, 18 flops
-#   chi^2: d - N, square, times 1/v, accumulate ->  4 instructions,  4 flops
+#   model: lifetime 1 mul, decaying rotation 2 mul + 2 fma, Gaussian 2 mul,
+#   sigma t 1 add, 1 - (sigma t)^2 1 fma, background and the two terms
+#   2 add + 1 fma                               -> 12 instructions, 16 flops
+#   chi^2: d - N, times 1/v, fused square-accumulate ->  3 instructions,  4 flops
 #   plus widening d, clamping and scaling the table index, range test
 #                                               ->  4 instructions,  0 flops
-FLOPS_PER_BIN_CHI2 = 22   # FMA = 2
-VALU_PER_BIN_CHI2 = 21    # instructions per bin of the per-bin loop
+FLOPS_PER_BIN_CHI2 = 20   # FMA = 2
+VALU_PER_BIN_CHI2 = 19    # instructions per bin of the per-bin loop
 BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
 COUNTERS = os.path.join(ROOT, "profiles", "eval_kernel_c2_stencil_counters.md")
 KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h"]

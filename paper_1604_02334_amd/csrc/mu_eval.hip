@@ -72,6 +72,7 @@ struct ShapeGeneric {
   __device__ static int nt(const TStruct &ts) { return ts.nt; }
   __device__ static int nf(const TStruct &ts, int k) { return ts.nf[k]; }
   __device__ static int prim(const TStruct &ts, int k, int f) { return ts.prim[k][f]; }
+  __device__ static constexpr bool fold(const TStruct &, int) { return false; }
 };
 
 template <int NT, int NF0, int P00, int P01, int NF1, int P10, int P11>
@@ -90,6 +91,12 @@ struct ShapeFixed {
   __device__ static constexpr int nf(const TStruct &, int k) { return k == 0 ? NF0 : (k == 1 ? NF1 : 0); }
   __device__ static constexpr int prim(const TStruct &, int k, int f) {
     return k == 0 ? (f == 0 ? P00 : P01) : (f == 0 ? P10 : P11);
+  }
+  // A scaled term se(lambda) tf(phi, nu) is one complex state: the
+  // exponential's step ratio joins the rotation's step and its value the
+  // rotation's amplitude, so the term is the state's real part.
+  __device__ static constexpr bool fold(const TStruct &, int k) {
+    return (k == 0 ? NF0 : NF1) == 2 && (k == 0 ? P00 : P10) == MU_SE && (k == 0 ? P01 : P11) == MU_TF;
   }
 };
 
@@ -427,6 +434,19 @@ __device__ __forceinline__ double cost_term(double d, double N, double iv_int, d
     if (WANT_DN) dN = 2.0;
     return 2.0 * N;
   }
+}
+
+// acc + the bin's cost term; chi^2 as acc + (d - N) ((d - N) / v) in one
+// fused step
+template <int COST, bool INT_DATA>
+__device__ __forceinline__ double cost_add(double acc, double d, double N, double iv_int) {
+  if (COST == MU_COST_CHI2) {
+    const double iv = INT_DATA ? iv_int : recip(d > 0.0 ? d : 1.0);
+    const double diff = d - N;
+    return fma(diff, diff * iv, acc);
+  }
+  double dN;
+  return acc + cost_term<COST, false, INT_DATA>(d, N, iv_int, dN);
 }
 
 template <typename CT>
@@ -824,6 +844,10 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
           c1[s] *= rE;
         }
         if (p == MU_STG) ecoef = fma(n0 * (coef[kt] * R[2 + kt]), kThird, ecoef);
+        if (Sh::fold(ts, kt)) {
+          c0[s + 1] *= c0[s];
+          c1[s + 1] *= c0[s];
+        }
       }
     }
 #pragma unroll
@@ -884,7 +908,9 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
           if (kt < n_terms) {
             const int nf = Sh::nf(ts, kt);
             const int s = kt * kMaxFT;
-            if (nf == 1) {
+            if (Sh::fold(ts, kt)) {
+              acc += s0[s + 1];
+            } else if (nf == 1) {
               if (Sh::prim(ts, kt, 0) == MU_STG) {
                 acc = fma(fma(-u[s], u[s], 1.0), s0[s], acc);
               } else {
@@ -908,8 +934,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         if constexpr (MODE == kModeModel) {
           S.model_out[idx] = N;
         } else {
-          double dN;
-          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, iv, dN);
+          lane_cost = cost_add<COST, kIntData>(lane_cost, d_cur, N, iv);
         }
       } else if constexpr (MODE != kModeGrad) {
         double A = 0.0;
@@ -929,8 +954,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         if constexpr (MODE == kModeModel) {
           S.model_out[idx] = N;
         } else {
-          double dN;
-          lane_cost += cost_term<COST, false, kIntData>(d_cur, N, iv, dN);
+          lane_cost = cost_add<COST, kIntData>(lane_cost, d_cur, N, iv);
         }
       } else {
         double val[kSlots], d0[kSlots], d1[kSlots];
@@ -988,7 +1012,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) {
         const int kt = s / kMaxFT, f = s % kMaxFT;
-        if (kt < n_terms && f < Sh::nf(ts, kt)) {
+        if (kt < n_terms && f < Sh::nf(ts, kt) && !(kScaled && f == 0 && Sh::fold(ts, kt))) {
           advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
           if (kScaled && Sh::prim(ts, kt, f) == MU_STG) u[s] += su[s];
         }
@@ -1060,6 +1084,10 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
             s0[s] *= L;
             if (p == MU_TF) s1[s] *= L;
             if (p == MU_SG || p == MU_STG) s1[s] *= rE;  // q: the Gaussian step also carries the lifetime
+          }
+          if (f == 1 && Sh::fold(ts, kt)) {
+            s0[s] *= s0[s - 1];
+            s1[s] *= s0[s - 1];
           }
         }
       }

@@ -557,6 +557,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
       const DevHisto &x = d->hh[j];
       for (int64_t i = 0; i < x.n; ++i) {
         const double v = h[j].counts[x.first + i];
+        d->max_count = std::max(d->max_count, v);
         if (d->f64)
           reinterpret_cast<double *>(buf.data())[x.off + i] = v;
         else
@@ -940,6 +941,7 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   a.n_units = (int32_t)n_units;
   a.cost_kind = cost_kind;
   a.anchor_every = anchor;
+  a.counts_in_table = !d->f64 && d->max_count < kInvTab;
   a.n_vec = n_vec;
   a.split_w = W;
   a.total = d->total;
@@ -1274,6 +1276,10 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     a.n_units = nb;
     a.cost_kind = cost_kind;
     a.anchor_every = ctx->anchor_every;
+    a.counts_in_table = 1;
+    for (int j = 0; j < n_jobs; ++j)
+      if ((ctx->specialize ? th[j]->shape : kShapeGeneric) == shp && (data[j]->f64 || data[j]->max_count >= kInvTab))
+        a.counts_in_table = 0;
     a.partial = static_cast<double *>(ctx->partial.ptr);
     const int ti = ctx->time_begin(grad ? MU_TIME_EVAL_GRAD : MU_TIME_EVAL_COST, ctx->stream);
     e = launch_eval(a, grad ? kModeGrad : kModeCost, data[0]->f64, shp, ctx->stream);

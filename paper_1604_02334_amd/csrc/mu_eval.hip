@@ -403,7 +403,9 @@ __device__ __forceinline__ double recip(double v) {
 
 // 1 / max(d, 1) of an integer count: from the workgroup's table (correctly
 // rounded) below kInvTab, else by recip().
+template <int TAB>
 __device__ __forceinline__ double inv_count(uint32_t raw, double d, const double *tab) {
+  if constexpr (TAB == 1) return tab[raw];  // the host checked: every count is below kInvTab
   double iv = tab[min(raw, (uint32_t)(kInvTab - 1))];
   // a wave-uniform test, so the rare large counts cost a skipped scalar branch
   if (__builtin_amdgcn_ballot_w64(raw >= (uint32_t)kInvTab) != 0) {
@@ -716,7 +718,7 @@ struct SegIn {
 };
 
 // One segment (see SegIn).
-template <int COST, int MODE, typename CT, typename Sh>
+template <int COST, int MODE, typename CT, typename Sh, int TAB>
 __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   const int tid = threadIdx.x;
   const DevTheory *th = S.th;
@@ -896,7 +898,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   // chi^2 on integer counts reads 1 / max(d, 1) from the workgroup's table
   constexpr bool kTable = COST == MU_COST_CHI2 && kIntData && MODE != kModeModel;
   auto inv_of = [&](CT raw, double d) -> double {
-    if constexpr (kTable) return inv_count((uint32_t)raw, d, S.inv_tab);
+    if constexpr (kTable) return inv_count<TAB>((uint32_t)raw, d, S.inv_tab);
     return 0.0;
   };
   auto bin_step = [&](int k, double d_cur, double iv) {
@@ -1173,7 +1175,9 @@ constexpr int eval_min_waves() {
   return (COST == MU_COST_CHI2 && MODE == kModeCost && Sh::kFixed) ? 6 : 1;
 }
 
-template <int COST, int MODE, typename CT, typename Sh>
+// TAB = 1: every count of the launch is an integer below kInvTab (the table
+// lookup needs neither clamp nor range test).
+template <int COST, int MODE, typename CT, typename Sh, int TAB>
 __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
   const int b = blockIdx.x;
   constexpr bool kTable = COST == MU_COST_CHI2 && sizeof(CT) == 4 && MODE != kModeModel;
@@ -1237,7 +1241,7 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
     S.map_row = H.map_row;
     S.anchor_every = a.anchor_every;
     S.inv_tab = inv_tab;
-    eval_segment<COST, MODE, CT, Sh>(S, slot);
+    eval_segment<COST, MODE, CT, Sh, TAB>(S, slot);
     if (!split) return;
     pos = seg_end;
     if (pos >= end) return;
@@ -1285,10 +1289,13 @@ __global__ __launch_bounds__(kBlock) void merge2_kernel(LaunchArgs first, int n_
 template <int COST, int MODE, typename Sh>
 hipError_t launch_shape(const LaunchArgs &a, int count_f64, hipStream_t s) {
   dim3 grid((a.n_units + kBlock / kWave - 1) / (kBlock / kWave)), block(kBlock);  // n_units counts units (waves)
+  constexpr bool kTab = COST == MU_COST_CHI2 && MODE != kModeModel;
   if (count_f64)
-    hipLaunchKernelGGL((eval_kernel<COST, MODE, double, ShapeGeneric>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, double, ShapeGeneric, 0>), grid, block, 0, s, a);
+  else if (kTab && a.counts_in_table)
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, Sh, kTab ? 1 : 0>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, Sh>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, Sh, 0>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1298,10 +1305,10 @@ int occupancy_shape(int count_f64) {
   hipError_t e;
   if (count_f64)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, double, ShapeGeneric>), kBlock, 0);
+        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, double, ShapeGeneric, 0>), kBlock, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, Sh>), kBlock, 0);
+        &nb, reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, Sh, 0>), kBlock, 0);
   return e == hipSuccess ? nb : 0;
 }
 

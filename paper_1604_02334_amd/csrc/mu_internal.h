@@ -20,8 +20,9 @@ constexpr int kRS = kArg0 + kMaxT * kMaxFT * 2;  // 30
 // by this many steps of 256 values.
 constexpr int kPrefetch = 4;
 // Entries of the per-workgroup table of 1 / max(d, 1) for integer counts
-// d < kInvTab (chi^2 kernels; FP64, 16 KiB of LDS).
-constexpr int kInvTab = 2048;
+// d < kInvTab (chi^2 kernels; FP64, 24 KiB of LDS: six workgroups of the
+// cost kernel still fit one compute unit's 160 KiB).
+constexpr int kInvTab = 3072;
 // Functions of p formed once per segment and shared through LDS (more use the
 // per-scalar path).
 constexpr int kFunStage = 32;
@@ -131,6 +132,7 @@ struct LaunchArgs {
   int32_t n_units;
   int32_t cost_kind;
   int32_t anchor_every;  // lane steps between exact re-evaluations, 1..256
+  int32_t counts_in_table;  // 1: every count of every job is an integer below kInvTab
   // Split launch (jobs == null, split_w > 0): n_vec vectors of `total`
   // fit-range bins each, cut into ranges of split_w bins, one per unit;
   // slot u + v * n_histo + h of `partial` belongs to unit u's segment of

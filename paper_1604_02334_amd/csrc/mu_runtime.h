@@ -113,6 +113,7 @@ struct mu_data {
   int max_row = 0;
   int64_t total = 0;
   int64_t longest = 0;     // bins of the longest fit range
+  double max_count = 0.0;  // largest fit-range count
   std::vector<mu::DevHisto> hh;
   std::deque<mu::TileSet> sets;  // one per tile size used so far (few); stable addresses
   mu::DevHisto *d_hh = nullptr;  // device copy of hh (split launches)

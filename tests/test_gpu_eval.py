@@ -499,12 +499,13 @@ def test_split_ranges_cross_histogram_and_vector_boundaries(ctx):
 
 
 def test_reciprocal_table_boundary_counts(ctx):
-    """Integer counts around the size of the reciprocal table
-    (2048) and far above it, interleaved so that one wave mixes table reads
-    with the hardware-reciprocal path; zeros take v = 1."""
+    """Integer counts around the size of the reciprocal table (3072) and far
+    above it, interleaved so that one wave mixes table reads with the
+    hardware-reciprocal path; zeros take v = 1. A dataset whose counts all
+    fit the table takes the lookup without range test: the same costs."""
     _say("reciprocal table boundary")
     th_d = synth.theory_exp_cos()
-    pattern = np.array([0, 1, 2, 3, 2046, 2047, 2048, 2049, 2050, 4095, 65535, 1000000, 16777216, 123456789, 7, 0])
+    pattern = np.array([0, 1, 2, 3, 2047, 2048, 3070, 3071, 3072, 3073, 4095, 65535, 1000000, 16777216, 123456789, 0])
     n = 50000
     cts = np.resize(pattern, n).astype(np.float64)
     hs = [{"n_bins": n, "dt": 0.0002, "t0_bin": 0.0, "first": 0, "last": n - 1, "map_row": 0}]
@@ -521,6 +522,20 @@ def test_reciprocal_table_boundary_counts(ctx):
         rg = model.grad(th_d, hs, [cts], P[v])
         sc = model.grad_abs_scale(th_d, hs, [cts], P[v])
         assert np.all(np.abs(g[v] - rg) <= REL * sc)
+    # largest count 3071: every lookup without the range test; one count of
+    # 3072 more sends the same bins through the tested lookup
+    small = np.resize(np.array([0, 1, 2, 3, 2047, 2048, 3070, 3071]), n).astype(np.float64)
+    big = small.copy()
+    big[-1] = 3072.0
+    th2, d_small = _mk(ctx, th_d, hs, [small])
+    d_big = api.Data(ctx, hs, [big])
+    for v in range(2):
+        c_small = api.chi2_eval(ctx, d_small, th2, P[v])[0]
+        c_big = api.chi2_eval(ctx, d_big, th2, P[v])[0]
+        ref_small = model.cost(th_d, hs, [small], P[v])
+        ref_big = model.cost(th_d, hs, [big], P[v])
+        assert abs(c_small - ref_small) <= REL * ref_small
+        assert abs(c_big - ref_big) <= REL * ref_big
 
 
 def test_eval_grad_argument_errors(ctx):

@@ -48,12 +48,13 @@ PEAK_FP64_TOPS = 39.3
 #   model: lifetime 1 mul, decaying rotation 2 mul + 2 fma, Gaussian 2 mul,
 #   sigma t 1 add, 1 - (sigma t)^2 1 fma, background and the two terms
 #   2 add + 1 fma                               -> 12 instructions, 16 flops
-#   chi^2: d - N, times 1/v, fused square-accumulate ->  3 instructions,  4 flops
-#   plus widening d and scaling the table index (every count of this data
-#   set is below the table size, so no clamp and no range test)
-#                                               ->  2 instructions,  0 flops
+#   chi^2: d - N (one fma with the decode of the stored 8 d), times 1/v,
+#   fused square-accumulate                     ->  3 instructions,  4 flops
+#   plus widening the stored 8 d (it is also the table entry's byte offset;
+#   every count of this data set is below the table size, so no clamp and no
+#   range test)                                 ->  1 instruction,   0 flops
 FLOPS_PER_BIN_CHI2 = 20   # FMA = 2
-VALU_PER_BIN_CHI2 = 17    # instructions per bin of the per-bin loop
+VALU_PER_BIN_CHI2 = 16    # instructions per bin of the per-bin loop
 BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
 COUNTERS = os.path.join(ROOT, "profiles", "eval_kernel_c2_stencil_counters.md")
 KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h"]

@@ -95,8 +95,8 @@ mu_status mu_ctx_synchronize(mu_ctx *ctx);
  * width dt > 0 (us), time origin t0_bin (t_n = (n - t0_bin) dt), inclusive fit
  * range [first, last], and the map row that selects its parameters P^j.
  * Counts must be finite and >= 0.  They are stored as 32-bit unsigned
- * integers when every value in every fit range is an integer below 2^32
- * (exact), else as FP64. */
+ * integers (8 d, exact) when every value in every fit range is an integer
+ * below 2^29, else as FP64. */
 typedef struct {
   const double *counts; /* host, n_bins values */
   int64_t n_bins;

@@ -327,7 +327,7 @@ static mu_status check_histos(const mu_histo *h, int32_t n, std::string &why, bo
         why = b;
         return MU_E_ARG;
       }
-      if (ints && (d != std::floor(d) || d >= 4294967296.0)) ints = false;
+      if (ints && (d != std::floor(d) || d >= kCountIntLimit)) ints = false;
     }
   }
   if (all_int) *all_int = ints;
@@ -561,7 +561,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
         if (d->f64)
           reinterpret_cast<double *>(buf.data())[x.off + i] = v;
         else
-          reinterpret_cast<uint32_t *>(buf.data())[x.off + i] = (uint32_t)v;
+          reinterpret_cast<uint32_t *>(buf.data())[x.off + i] = (uint32_t)v * kCountScale;
       }
     }
     e = hipMemcpy(d->counts, buf.data(), buf.size(), hipMemcpyHostToDevice);

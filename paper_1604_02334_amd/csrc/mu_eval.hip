@@ -403,14 +403,18 @@ __device__ __forceinline__ double recip(double v) {
 
 // 1 / max(d, 1) of an integer count: from the workgroup's table (correctly
 // rounded) below kInvTab, else by recip().
+// raw = 8 d is the entry's byte offset; x is raw widened.
 template <int TAB>
-__device__ __forceinline__ double inv_count(uint32_t raw, double d, const double *tab) {
-  if constexpr (TAB == 1) return tab[raw];  // the host checked: every count is below kInvTab
-  double iv = tab[min(raw, (uint32_t)(kInvTab - 1))];
+__device__ __forceinline__ double inv_count(uint32_t raw, double x, const double *tab) {
+  const char *base = reinterpret_cast<const char *>(tab);
+  // the host checked: every count is below kInvTab
+  if constexpr (TAB == 1) return *reinterpret_cast<const double *>(base + raw);
+  constexpr uint32_t kEnd = (uint32_t)kInvTab * kCountScale;
+  double iv = *reinterpret_cast<const double *>(base + min(raw, kEnd - kCountScale));
   // a wave-uniform test, so the rare large counts cost a skipped scalar branch
-  if (__builtin_amdgcn_ballot_w64(raw >= (uint32_t)kInvTab) != 0) {
+  if (__builtin_amdgcn_ballot_w64(raw >= kEnd) != 0) {
     asm volatile("");  // keeps the branch: not speculated into every bin
-    if (raw >= (uint32_t)kInvTab) iv = recip(d);
+    if (raw >= kEnd) iv = recip(x * kCountUnscale);
   }
   return iv;
 }
@@ -439,21 +443,17 @@ __device__ __forceinline__ double cost_term(double d, double N, double iv_int, d
 }
 
 // acc + the bin's cost term; chi^2 as acc + (d - N) ((d - N) / v) in one
-// fused step
+// fused step. x is the stored count widened (8 d for integer storage), so
+// d - N is one fused step too.
 template <int COST, bool INT_DATA>
-__device__ __forceinline__ double cost_add(double acc, double d, double N, double iv_int) {
+__device__ __forceinline__ double cost_add(double acc, double x, double N, double iv_int) {
   if (COST == MU_COST_CHI2) {
-    const double iv = INT_DATA ? iv_int : recip(d > 0.0 ? d : 1.0);
-    const double diff = d - N;
+    const double diff = INT_DATA ? fma(x, kCountUnscale, -N) : x - N;
+    const double iv = INT_DATA ? iv_int : recip(x > 0.0 ? x : 1.0);
     return fma(diff, diff * iv, acc);
   }
   double dN;
-  return acc + cost_term<COST, false, INT_DATA>(d, N, iv_int, dN);
-}
-
-template <typename CT>
-__device__ __forceinline__ double load_count(const void *counts, int64_t i) {
-  return (double)(static_cast<const CT *>(counts)[i]);
+  return acc + cost_term<COST, false, INT_DATA>(INT_DATA ? x * kCountUnscale : x, N, iv_int, dN);
 }
 
 __device__ __forceinline__ DevJob job_of(const LaunchArgs &a, int b, int &job) {
@@ -897,11 +897,12 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   // one bin: value, cost term (or model value), gradient, then advance
   // chi^2 on integer counts reads 1 / max(d, 1) from the workgroup's table
   constexpr bool kTable = COST == MU_COST_CHI2 && kIntData && MODE != kModeModel;
-  auto inv_of = [&](CT raw, double d) -> double {
-    if constexpr (kTable) return inv_count<TAB>((uint32_t)raw, d, S.inv_tab);
+  auto inv_of = [&](CT raw, double x) -> double {
+    if constexpr (kTable) return inv_count<TAB>((uint32_t)raw, x, S.inv_tab);
     return 0.0;
   };
-  auto bin_step = [&](int k, double d_cur, double iv) {
+  // x_cur: the stored count widened (8 d for integer storage)
+  auto bin_step = [&](int k, double x_cur, double iv) {
     const int64_t idx = idx0 + (int64_t)k * kWave;
       if constexpr (kScaled) {
         double acc = E + nbkg;
@@ -936,7 +937,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         if constexpr (MODE == kModeModel) {
           S.model_out[idx] = N;
         } else {
-          lane_cost = cost_add<COST, kIntData>(lane_cost, d_cur, N, iv);
+          lane_cost = cost_add<COST, kIntData>(lane_cost, x_cur, N, iv);
         }
       } else if constexpr (MODE != kModeGrad) {
         double A = 0.0;
@@ -956,7 +957,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         if constexpr (MODE == kModeModel) {
           S.model_out[idx] = N;
         } else {
-          lane_cost = cost_add<COST, kIntData>(lane_cost, d_cur, N, iv);
+          lane_cost = cost_add<COST, kIntData>(lane_cost, x_cur, N, iv);
         }
       } else {
         double val[kSlots], d0[kSlots], d1[kSlots];
@@ -982,6 +983,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         }
         const double N = fma(n0 * E, 1.0 + A, nbkg);
         double dN;
+        const double d_cur = kIntData ? x_cur * kCountUnscale : x_cur;
         lane_cost += cost_term<COST, true, kIntData>(d_cur, N, iv, dN);
         const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
         const double rNE = rE * n0;  // r N0 e^(-t/tau)
@@ -1101,15 +1103,15 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     for (; k + kPrefetch <= k1; k += kPrefetch, nxt += kPrefetch * kWave) {  // uniform trip count
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i) {
-        const double d = (double)dq[i];  // widened (and looked up) first: the load can reuse its register
-        const double iv = inv_of(dq[i], d);
+        const double x = (double)dq[i];  // widened (and looked up) first: the load can reuse its register
+        const double iv = inv_of(dq[i], x);
         if constexpr (MODE != kModeModel) {
           dq[i] = nxt[i * kWave];
           // keep the read here, a full kPrefetch steps before its use (the
           // scheduler would otherwise sink it towards the end of the loop)
           __builtin_amdgcn_sched_barrier(0);
         }
-        bin_step(k + i, d, iv);
+        bin_step(k + i, x, iv);
       }
     }
     // only the last segment has a tail: under kPrefetch uniform steps, then

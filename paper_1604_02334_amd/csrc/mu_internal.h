@@ -23,6 +23,12 @@ constexpr int kPrefetch = 4;
 // d < kInvTab (chi^2 kernels; FP64, 24 KiB of LDS: six workgroups of the
 // cost kernel still fit one compute unit's 160 KiB).
 constexpr int kInvTab = 3072;
+// Integer counts d < 2^29 are stored as 32-bit values 8 d: the byte offset of
+// their entry in that table (no shift before the lookup); kernels take
+// d = stored / 8, which is exact.
+constexpr uint32_t kCountScale = 8;
+constexpr double kCountUnscale = 0.125;
+constexpr double kCountIntLimit = 536870912.0;  // 2^29
 // Functions of p formed once per segment and shared through LDS (more use the
 // per-scalar path).
 constexpr int kFunStage = 32;

@@ -168,8 +168,8 @@ __global__ __launch_bounds__(256) void gen_kernel(unsigned long long seed, unsig
 // (two equations m = N0 e + Nbkg, e the lifetime decay averaged over the
 // window) and ebar_b the decay averaged over rebinned bin b.  m1 and m2 are
 // also written for the default start.
-// Inputs either from datasets (src: one uint32 count array per sample) or from
-// the generator's contiguous FP32 counts (contig).
+// Inputs either from datasets (src: one count array per sample, 32-bit values
+// holding 8 d) or from the generator's contiguous FP32 counts (contig).
 __global__ __launch_bounds__(256) void prep_kernel(const uint32_t *const *src, const float *contig, int rebin, int n,
                                                    unsigned short *X, double *n0_out, double *m_first,
                                                    double *m_last) {
@@ -185,7 +185,8 @@ __global__ __launch_bounds__(256) void prep_kernel(const uint32_t *const *src, c
   for (int q = 0; q < kCoarse / 256; ++q) {
     const int b = threadIdx.x + q * 256;
     double v = 0.0;
-    for (int r = 0; r < rebin; ++r) v += pu ? (double)pu[b * rebin + r] : (double)pf[b * rebin + r];
+    for (int r = 0; r < rebin; ++r)
+      v += pu ? (double)pu[b * rebin + r] * kCountUnscale : (double)pf[b * rebin + r];
     c[q] = v;
     if (b < kWin) w1 += v;
     if (b >= kCoarse - kWin) w2 += v;

@@ -510,7 +510,7 @@ def test_reciprocal_table_boundary_counts(ctx):
     cts = np.resize(pattern, n).astype(np.float64)
     hs = [{"n_bins": n, "dt": 0.0002, "t0_bin": 0.0, "first": 0, "last": n - 1, "map_row": 0}]
     th, d = _mk(ctx, th_d, hs, [cts])
-    assert d.is_f64 is False  # every value is an integer below 2^32: 32-bit storage
+    assert d.is_f64 is False  # every value is an integer below 2^29: 32-bit storage
     p = np.array([3000.0, 5.0, 0.2, 0.7, 3.3, 0.4])
     P = np.stack([p, perturbed(p, 0.1, 90)])
     got = api.chi2_eval(ctx, d, th, P)
@@ -522,6 +522,16 @@ def test_reciprocal_table_boundary_counts(ctx):
         rg = model.grad(th_d, hs, [cts], P[v])
         sc = model.grad_abs_scale(th_d, hs, [cts], P[v])
         assert np.all(np.abs(g[v] - rg) <= REL * sc)
+    # the largest integer kept in 32-bit storage (as 8 d: 2^29 - 1) and the
+    # first one that is not
+    for top, f64 in ((2.0 ** 29 - 1, False), (2.0 ** 29, True)):
+        c = cts.copy()
+        c[5] = top
+        dd = api.Data(ctx, hs, [c])
+        assert dd.is_f64 is f64
+        got_top = api.chi2_eval(ctx, dd, th, P[0])[0]
+        ref_top = model.cost(th_d, hs, [c], P[0])
+        assert abs(got_top - ref_top) <= REL * ref_top
     # largest count 3071: every lookup without the range test; one count of
     # 3072 more sends the same bins through the tested lookup
     small = np.resize(np.array([0, 1, 2, 3, 2047, 2048, 3070, 3071]), n).astype(np.float64)

@@ -155,6 +155,21 @@ extern "C" mu_status mu_ctx_create(int device, void *hip_stream, unsigned flags,
     delete c;
     return MU_E_DEVICE;
   }
+  // 1 / max(i, 1) for i < kInvTab, correctly rounded (IEEE division), copied
+  // into LDS by every chi^2 evaluation workgroup
+  {
+    std::vector<double> inv(kInvTab);
+    for (int i = 0; i < kInvTab; ++i) inv[i] = 1.0 / (double)(i > 0 ? i : 1);
+    hipError_t e = hipMalloc(&c->d_inv, inv.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(c->d_inv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (c->d_inv) hipFree(c->d_inv);
+      hipEventDestroy(c->staging_free);
+      if (c->own_stream) hipStreamDestroy(c->stream);
+      delete c;
+      return MU_E_DEVICE;
+    }
+  }
   *out = c;
   return MU_OK;
 }
@@ -168,6 +183,7 @@ extern "C" mu_status mu_ctx_destroy(mu_ctx *ctx) {
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   ctx->release_all();
+  if (ctx->d_inv) hipFree(ctx->d_inv);
   if (ctx->staging_free) hipEventDestroy(ctx->staging_free);
   for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
@@ -942,6 +958,7 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   a.cost_kind = cost_kind;
   a.anchor_every = anchor;
   a.counts_in_table = !d->f64 && d->max_count < kInvTab;
+  a.inv_src = ctx->d_inv;
   a.n_vec = n_vec;
   a.split_w = W;
   a.total = d->total;
@@ -1276,6 +1293,7 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     a.n_units = nb;
     a.cost_kind = cost_kind;
     a.anchor_every = ctx->anchor_every;
+    a.inv_src = ctx->d_inv;
     a.counts_in_table = 1;
     for (int j = 0; j < n_jobs; ++j)
       if ((ctx->specialize ? th[j]->shape : kShapeGeneric) == shp && (data[j]->f64 || data[j]->max_count >= kInvTab))

@@ -1183,9 +1183,13 @@ template <int COST, int MODE, typename CT, typename Sh, int TAB>
 __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
   const int b = blockIdx.x;
   constexpr bool kTable = COST == MU_COST_CHI2 && sizeof(CT) == 4 && MODE != kModeModel;
-  __shared__ double inv_tab[kTable ? kInvTab : 1];
+  __shared__ __align__(16) double inv_tab[kTable ? kInvTab : 2];
   if constexpr (kTable) {
-    for (int i = threadIdx.x; i < kInvTab; i += kBlock) inv_tab[i] = 1.0 / (double)(i > 0 ? i : 1);
+    // the context's table, 16 B per load and store
+    static_assert(kInvTab % 2 == 0, "table copied in pairs");
+    const double2 *src = reinterpret_cast<const double2 *>(a.inv_src);
+    double2 *dst = reinterpret_cast<double2 *>(inv_tab);
+    for (int i = threadIdx.x; i < kInvTab / 2; i += kBlock) dst[i] = src[i];
     __syncthreads();
   }
   // each wave is one unit of work; no workgroup barrier after this point

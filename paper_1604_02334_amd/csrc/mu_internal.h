@@ -139,6 +139,7 @@ struct LaunchArgs {
   int32_t cost_kind;
   int32_t anchor_every;  // lane steps between exact re-evaluations, 1..256
   int32_t counts_in_table;  // 1: every count of every job is an integer below kInvTab
+  const double *inv_src;    // [kInvTab] 1 / max(i, 1) (device), copied to LDS by chi^2 launches
   // Split launch (jobs == null, split_w > 0): n_vec vectors of `total`
   // fit-range bins each, cut into ranges of split_w bins, one per unit;
   // slot u + v * n_histo + h of `partial` belongs to unit u's segment of

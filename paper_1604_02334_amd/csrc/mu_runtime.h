@@ -69,6 +69,7 @@ struct mu_ctx {
   int64_t pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const;
   int specialize = 1;  // use the compiled shape kernels when a theory matches one
   hipEvent_t staging_free = nullptr;  // recorded after each upload from `staging`
+  double *d_inv = nullptr;  // [kInvTab] 1 / max(i, 1): source of the kernels' LDS table
   // partial_aux: the gradient pass's slots in mu_chi2_eval_grad
   mu::DevBuf partial, partial_aux, dparams, dout, djobs;
   mu::HostBuf staging, staging_out;

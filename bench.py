@@ -55,8 +55,13 @@ PEAK_FP64_TOPS = 39.3
 #   range test)                                 ->  1 instruction,   0 flops
 FLOPS_PER_BIN_CHI2 = 20   # FMA = 2
 VALU_PER_BIN_CHI2 = 16    # instructions per bin of the per-bin loop
+# Per bin of the gradient pass (N, dN/dR for the 30 resolved scalars of the
+# shape, chi^2 and r dN/dR accumulated), from the same loop's ISA: 56 fma,
+# 120 mul, 24 add per four bins, and 52 FP64 instructions per bin.
+FLOPS_PER_BIN_GRAD = 64
+VALU_PER_BIN_GRAD = 52
 BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
-COUNTERS = os.path.join(ROOT, "profiles", "eval_kernel_c2_stencil_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "eval_grad_cost_kernel_c2_step_counters.md")
 KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h"]
 
 
@@ -81,7 +86,7 @@ def _counters():
     if not m or m.group(1) != _kernel_hash():
         return None
     out = {}
-    for key in ("hbm_bytes_per_launch", "valu_instr_per_bin"):
+    for key in ("hbm_bytes_per_launch", "valu_instr_per_launch"):
         mm = re.search(key + r": `([0-9.e+]+)`", text)
         if mm:
             out[key] = float(mm.group(1))
@@ -468,6 +473,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0,
                     help="with --stencil-only: bins per wave (skips the autotuner; 0 keeps it)")
     ap.add_argument("--anchor", type=int, default=0, help="with --stencil-only and --tile: anchor interval")
+    ap.add_argument("--tuned", default="",
+                    help="W:anchor,W:anchor of the stencil and gradient passes (an earlier run's tuned_stencil and "
+                         "tuned_grad) in place of the autotuner")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -513,6 +521,12 @@ def main():
         if args.anchor:
             ctx.anchor = args.anchor
         tune_eval = (args.tile, ctx.anchor)
+    elif args.tuned:
+        # replay the launch shapes of an earlier run: stencil W:anchor,gradient W:anchor
+        (ws, a_s), (wg, a_g) = [tuple(int(x) for x in part.split(":")) for part in args.tuned.split(",")]
+        api.autotune_set(ctx, data, th, s_dev.shape[0], ws, a_s)
+        api.autotune_set(ctx, data, th, 1, wg, a_g, grad=True)
+        tune_eval, tune_grad = (ws, a_s), (wg, a_g)
     else:
         # measured tile / anchor choice for both launches (untimed)
         tune_eval = api.autotune(ctx, data, th, s_dev)
@@ -542,10 +556,24 @@ def main():
         step()
     torch.cuda.synchronize()
     ctx.timing(False)
-    n_cost, ms_cost = ctx.timing_read("cost")
-    n_grad, ms_grad = ctx.timing_read("grad")
+    n_gc, ms_gc = ctx.timing_read("grad_cost")
     n_merge, ms_merge = ctx.timing_read("merge")
-    assert n_cost == args.steps and n_grad == args.steps and n_merge == args.steps  # one merge launch per step
+    # one evaluation launch (gradient and stencil together) and one merge launch per step
+    assert n_gc == args.steps and n_merge == args.steps
+
+    # the two passes as separate launches, for comparison (same tuned shapes)
+    def kernel_us(kind, fn, n=20):
+        fn()
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        ctx.timing(False)
+        c, ms = ctx.timing_read(kind)
+        return ms / c * 1e3
+    sep_cost_us = kernel_us("cost", lambda: api.chi2_eval(ctx, data, th, s_dev))
+    sep_grad_us = kernel_us("grad", lambda: api.chi2_grad(ctx, data, th, p_dev))
 
     # single-vector latency (cost only, host in and out)
     host_p = p0[None]
@@ -559,10 +587,15 @@ def main():
     bins_per_step = (1 + stencil.shape[0]) * n_bins
     ms_per_step = wall / args.steps * 1e3
     value = bins_per_step / (wall / args.steps) / 1e9
-    k_ms = ms_cost / n_cost
-    k_bins = stencil.shape[0] * n_bins
-    rate = k_bins / (k_ms * 1e-3)  # bins per second in the stencil kernel
-    achieved = FLOPS_PER_BIN_CHI2 * rate / 1e12
+    # the dominant kernel: the step's single evaluation launch
+    k_ms = ms_gc / n_gc
+    c_bins = stencil.shape[0] * n_bins  # cost-pass bin evaluations per launch
+    g_bins = n_bins                     # gradient-pass bin evaluations per launch
+    k_bins = c_bins + g_bins
+    k_flops = FLOPS_PER_BIN_CHI2 * c_bins + FLOPS_PER_BIN_GRAD * g_bins
+    k_instr = VALU_PER_BIN_CHI2 * c_bins + VALU_PER_BIN_GRAD * g_bins
+    achieved = k_flops / (k_ms * 1e-3) / 1e12
+    issue = k_instr / (k_ms * 1e-3) / 1e12  # T lane-instructions per second
     ctr = _counters()
     out = {
         "metric": "chi2 Gbin/s (FP64 acc, 1e-10 rel)",
@@ -583,23 +616,28 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "traffic": ctr.get("hbm_bytes_per_launch") if ctr else None,
-                     "kernel": "eval_kernel<chi2, cost, uint32, exp*cos + stg>", "kernel_ms": round(k_ms, 5),
-                     "flops_per_bin": FLOPS_PER_BIN_CHI2, "bins_per_launch": k_bins,
+                     "kernel": "eval_grad_cost_kernel<chi2, uint32, exp*cos + stg> (gradient at 1 vector + "
+                               "cost at 104 vectors)",
+                     "kernel_ms": round(k_ms, 5),
+                     "flops_per_bin": {"cost": FLOPS_PER_BIN_CHI2, "grad": FLOPS_PER_BIN_GRAD},
+                     "bins_per_launch": {"cost": c_bins, "grad": g_bins},
+                     "flops_per_launch": k_flops,
                      "algorithmic_bytes_per_launch": BYTES_PER_BIN * k_bins,
                      # the binding limit of this instruction mix: VALU issue
                      "valu_issue": {
-                         "instr_per_bin": VALU_PER_BIN_CHI2,
-                         "frac": round(VALU_PER_BIN_CHI2 * rate / 1e12 / PEAK_FP64_TOPS, 4),
-                         "measured_instr_per_bin": ctr.get("valu_instr_per_bin") if ctr else None,
-                         "measured_frac": (round(ctr["valu_instr_per_bin"] * rate / 1e12 / PEAK_FP64_TOPS, 4)
-                                           if ctr and "valu_instr_per_bin" in ctr else None),
+                         "instr_per_bin": {"cost": VALU_PER_BIN_CHI2, "grad": VALU_PER_BIN_GRAD},
+                         "frac": round(issue / PEAK_FP64_TOPS, 4),
+                         "measured_instr_per_launch": ctr.get("valu_instr_per_launch") if ctr else None,
+                         "measured_frac": (round(ctr["valu_instr_per_launch"] / (k_ms * 1e-3) / 1e12
+                                                 / PEAK_FP64_TOPS, 4)
+                                           if ctr and "valu_instr_per_launch" in ctr else None),
                          "peak_tops": PEAK_FP64_TOPS,
-                         "attainable_flop_frac": round(FLOPS_PER_BIN_CHI2 / VALU_PER_BIN_CHI2 * PEAK_FP64_TOPS
-                                                       / PEAK_FP64_TFLOPS, 4)}},
-        "extra": {"stencil_kernel_gbin_s": round(rate / 1e9, 2),
+                         "attainable_flop_frac": round(k_flops / k_instr * PEAK_FP64_TOPS / PEAK_FP64_TFLOPS, 4)}},
+        "extra": {"step_kernel_gbin_s": round(k_bins / (k_ms * 1e-3) / 1e9, 2),
+                  "separate_launches_us": {"stencil": round(sep_cost_us, 2), "grad": round(sep_grad_us, 2)},
+                  "stencil_kernel_gbin_s": round(c_bins / (sep_cost_us * 1e-6) / 1e9, 2),
                   "tuned_stencil": {"tile": tune_eval[0], "anchor": tune_eval[1]},
                   "tuned_grad": {"tile": tune_grad[0], "anchor": tune_grad[1]},
-                  "grad_kernel_us": round(ms_grad / n_grad * 1e3, 2),
                   "merge_kernels_us_per_step": round(ms_merge / args.steps * 1e3, 2),
                   "single_eval_host_latency_us": round(lat_us, 2)},
     }

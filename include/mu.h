@@ -192,8 +192,9 @@ mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu
  * n_grad vectors params_grad ([n_grad][n_par]) as mu_chi2_grad, and the cost
  * at the n_cost vectors params_cost ([n_cost][n_par]) as mu_chi2_eval (trial
  * or finite-difference points; Sec. 4 and Table 1 count such evaluations).
- * Both passes run on the context's stream and share one merge launch.
- * Results are bitwise those of the two separate calls.  Outputs:
+ * Both passes run on the context's stream as one evaluation launch (chi^2,
+ * compiled theory shapes, 32-bit counts; otherwise two launches) and share
+ * one merge launch.  Results are bitwise those of the two separate calls.  Outputs:
  * cost_grad [n_grad], grad [n_grad][n_par], cost [n_cost].  mem applies to
  * all parameter and output arrays.  Errors as mu_chi2_eval. */
 mu_status mu_chi2_eval_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
@@ -255,7 +256,8 @@ typedef enum {
   MU_TIME_EVAL_COST = 0,  /* evaluation kernels, cost only */
   MU_TIME_EVAL_GRAD = 1,  /* evaluation kernels, cost and gradient */
   MU_TIME_EVAL_MODEL = 2, /* mu_model_eval kernels */
-  MU_TIME_MERGE = 3       /* merge kernels (both modes) */
+  MU_TIME_MERGE = 3,      /* merge kernels (both modes) */
+  MU_TIME_EVAL_GRAD_COST = 4 /* mu_chi2_eval_grad's single evaluation launch */
 } mu_time_kind;
 mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable);
 /* Waits for the recorded launches of `kind` to finish and writes how many
@@ -275,6 +277,15 @@ mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_launches, dou
 mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
                       const double *params, int32_t n_vec, unsigned mem, int32_t grad,
                       int32_t *best_tile, int32_t *best_anchor, double *best_us);
+
+/* Record (tile_bins, anchor_every) for later single-dataset launches of
+ * n_vec vectors over `data` with this theory shape, cost and mode (gradient
+ * when grad != 0), as if mu_autotune had chosen it: replays a choice measured
+ * earlier (another process, a stored configuration) without measuring.
+ * MU_E_ARG for tile_bins outside [64, 2^26], anchor_every outside [1, 256],
+ * n_vec < 1 or an unknown cost kind. */
+mu_status mu_autotune_set(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                          int32_t n_vec, int32_t grad, int32_t tile_bins, int32_t anchor_every);
 
 /* ----------------------------------------------------------------- fitting */
 

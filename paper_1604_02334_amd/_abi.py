@@ -104,6 +104,7 @@ def lib():
         "mu_ctx_timing_read": (S, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mu_autotune": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, C.c_int32, C.POINTER(C.c_int32),
                             C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "mu_autotune_set": (S, [vp, vp, vp, S, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "mu_histo_check": (S, [C.POINTER(mu_histo), C.c_int32, C.c_char_p, C.c_int32]),
         "mu_data_create": (S, [vp, C.POINTER(mu_histo), C.c_int32, C.POINTER(vp)]),
         "mu_data_destroy": (S, [vp]),
@@ -134,7 +135,8 @@ def exported_symbols():
     """Names declared in include/mu.h that the binding expects."""
     return sorted(["mu_abi_version", "mu_status_string", "mu_ctx_create", "mu_ctx_destroy", "mu_ctx_last_error",
                    "mu_ctx_synchronize", "mu_ctx_set_tile", "mu_ctx_get_tile", "mu_ctx_set_anchor", "mu_ctx_get_anchor",
-                   "mu_ctx_set_specialize", "mu_ctx_timing", "mu_ctx_timing_read", "mu_autotune", "mu_histo_check", "mu_data_create",
+                   "mu_ctx_set_specialize", "mu_ctx_timing", "mu_ctx_timing_read", "mu_autotune", "mu_autotune_set",
+                   "mu_histo_check", "mu_data_create",
                    "mu_data_destroy", "mu_data_bins", "mu_data_histos", "mu_data_is_f64", "mu_theory_check",
                    "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_chi2_eval", "mu_chi2_grad",
                    "mu_chi2_eval_grad", "mu_chi2_batch", "mu_model_eval", "mu_fit_batch",

@@ -85,11 +85,11 @@ class Context:
         """Start (discarding earlier records) or stop event timing of kernel launches."""
         _check(A.lib().mu_ctx_timing(self.h, 1 if on else 0), self.h, "mu_ctx_timing")
 
-    _TIME_KINDS = {"cost": 0, "grad": 1, "model": 2, "merge": 3}
+    _TIME_KINDS = {"cost": 0, "grad": 1, "model": 2, "merge": 3, "grad_cost": 4}
 
     def timing_read(self, kind):
         """(launch count, summed milliseconds) of the recorded launches of `kind`
-        ('cost', 'grad', 'model' or 'merge')."""
+        ('cost', 'grad', 'model', 'merge' or 'grad_cost')."""
         n = C.c_int32()
         ms = C.c_double()
         _check(A.lib().mu_ctx_timing_read(self.h, self._TIME_KINDS[kind], C.byref(n), C.byref(ms)), self.h,
@@ -412,6 +412,13 @@ def autotune(ctx, data, theory, params, cost="chi2", grad=False):
         _check(L.mu_autotune(ctx.h, data.h, theory.h, _cost_code(cost), p.ctypes.data, p.shape[0], A.MU_MEM_HOST,
                              1 if grad else 0, C.byref(bt), C.byref(ba), C.byref(us)), ctx.h, "mu_autotune")
     return bt.value, ba.value, us.value
+
+
+def autotune_set(ctx, data, theory, n_vec, tile, anchor, cost="chi2", grad=False):
+    """Record a (tile, anchor) choice for launches of n_vec vectors over this
+    dataset and theory, as if autotune had measured it."""
+    _check(A.lib().mu_autotune_set(ctx.h, data.h, theory.h, _cost_code(cost), int(n_vec), 1 if grad else 0,
+                                   int(tile), int(anchor)), ctx.h, "mu_autotune_set")
 
 
 def fit_batch(ctx, datas, theories, start, cost="chi2", fixed=None, analytic_grad=True, batched=True,

@@ -230,7 +230,7 @@ extern "C" mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable) {
 
 extern "C" mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_launches, double *total_ms) {
   if (!ctx) return MU_E_ARG;
-  if (kind < MU_TIME_EVAL_COST || kind > MU_TIME_MERGE || !n_launches || !total_ms) {
+  if (kind < MU_TIME_EVAL_COST || kind > MU_TIME_EVAL_GRAD_COST || !n_launches || !total_ms) {
     set_err(ctx, "mu_ctx_timing_read: unknown kind %d or NULL output", kind);
     return MU_E_ARG;
   }
@@ -911,12 +911,13 @@ static mu_status check_eval_args(mu_ctx *ctx, int cost_kind, unsigned mem, int32
 // A launched evaluation whose merge is still to be enqueued.
 struct Pending {
   LaunchArgs a;
-  int mode = 0, n_vec = 0;
+  int mode = 0, n_vec = 0, shape = 0, f64 = 0;
 };
 
+// Prepares (and, unless launch is false, enqueues) one evaluation launch.
 static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp,
                              int32_t n_vec, double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s,
-                             DevBuf &partial, Pending &pend) {
+                             DevBuf &partial, Pending &pend, bool launch = true) {
   mu_status st;
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
   int anchor = ctx->anchor_every;
@@ -963,6 +964,12 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   a.split_w = W;
   a.total = d->total;
   a.partial = static_cast<double *>(partial.ptr);
+  pend.a = a;
+  pend.mode = mode;
+  pend.n_vec = n_vec;
+  pend.shape = shape;
+  pend.f64 = d->f64;
+  if (!launch) return MU_OK;
   int ti = ctx->time_begin(mode == kModeGrad    ? MU_TIME_EVAL_GRAD
                            : mode == kModeModel ? MU_TIME_EVAL_MODEL
                                                 : MU_TIME_EVAL_COST,
@@ -970,9 +977,6 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   hipError_t e = launch_eval(a, mode, d->f64, shape, s);
   ctx->time_end(ti, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
-  pend.a = a;
-  pend.mode = mode;
-  pend.n_vec = n_vec;
   return MU_OK;
 }
 
@@ -1073,16 +1077,32 @@ mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int 
     dg = dcg + n_grad;
     dcc = dg + n_pg;
   }
-  // both passes on the context's stream (their own slot buffers), then one
-  // merge launch for both: the gradient job's merge latency hides behind the
-  // cost jobs' merges
+  // both passes on the context's stream (their own slot buffers) as one
+  // launch where a compiled kernel exists (else two), then one merge launch
+  // for both: the gradient job's merge latency hides behind the cost jobs'
+  // merges
   Pending pg_, pc_;
   if ((st = eval_launch(ctx, d, th, cost_kind, dpg, n_grad, dcg, nullptr, dg, nullptr, kModeGrad, ctx->stream,
-                        ctx->partial_aux, pg_)) != MU_OK)
+                        ctx->partial_aux, pg_, false)) != MU_OK)
     return st;
   if ((st = eval_launch(ctx, d, th, cost_kind, dpc, n_cost, dcc, nullptr, nullptr, nullptr, kModeCost, ctx->stream,
-                        ctx->partial, pc_)) != MU_OK)
+                        ctx->partial, pc_, false)) != MU_OK)
     return st;
+  if (eval_grad_cost_fused(pg_.f64, pg_.shape, cost_kind)) {
+    const int ti = ctx->time_begin(MU_TIME_EVAL_GRAD_COST, ctx->stream);
+    e = launch_eval_grad_cost(pg_.a, pc_.a, pg_.f64, pg_.shape, ctx->stream);
+    ctx->time_end(ti, ctx->stream);
+  } else {
+    int ti = ctx->time_begin(MU_TIME_EVAL_GRAD, ctx->stream);
+    e = launch_eval(pg_.a, kModeGrad, pg_.f64, pg_.shape, ctx->stream);
+    ctx->time_end(ti, ctx->stream);
+    if (e == hipSuccess) {
+      ti = ctx->time_begin(MU_TIME_EVAL_COST, ctx->stream);
+      e = launch_eval(pc_.a, kModeCost, pc_.f64, pc_.shape, ctx->stream);
+      ctx->time_end(ti, ctx->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
   const int ti = ctx->time_begin(MU_TIME_MERGE, ctx->stream);
   e = launch_merge_grad_cost(pg_.a, n_grad, pc_.a, n_cost, ctx->stream);
   ctx->time_end(ti, ctx->stream);
@@ -1334,6 +1354,37 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
 
 // ------------------------------------------------------------------ tuning
 
+// The tuned (tile, anchor) of single-dataset launches of this theory's shape,
+// mode, cost and size.
+static void remember_tuned(mu_ctx *ctx, const mu_theory *th, int mode, int cost_kind, int64_t work, int tile,
+                           int anchor) {
+  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
+  const int key = tune_key(shape, mode, cost_kind, 1, work);
+  for (auto &t : ctx->tuned)
+    if (t.key == key) {
+      t.tile = tile;
+      t.anchor = anchor;
+      return;
+    }
+  ctx->tuned.push_back({key, tile, anchor});
+}
+
+extern "C" mu_status mu_autotune_set(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                                     int32_t n_vec, int32_t grad, int32_t tile_bins, int32_t anchor_every) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (n_vec < 1 || (cost_kind != MU_COST_CHI2 && cost_kind != MU_COST_POISSON) || tile_bins < kWave ||
+      tile_bins > kMaxSplit || anchor_every < 1 || anchor_every > 256) {
+    set_err(ctx, "autotune_set needs n_vec >= 1, a cost kind, tile_bins in [%d, %d] and anchor_every in [1, 256]",
+            kWave, kMaxSplit);
+    return MU_E_ARG;
+  }
+  remember_tuned(ctx, th, grad ? kModeGrad : kModeCost, cost_kind, (int64_t)n_vec * data->total, tile_bins,
+                 anchor_every);
+  return MU_OK;
+}
+
 extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
                                  const double *params, int32_t n_vec, unsigned mem, int32_t grad,
                                  int32_t *best_tile, int32_t *best_anchor, double *best_us) {
@@ -1428,16 +1479,7 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
     return MU_E_DEVICE;
   }
   // remember the choice for launches of this shape, mode, cost and size
-  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
-  const int key = tune_key(shape, mode, cost_kind, 1, work_all);
-  bool found = false;
-  for (auto &t : ctx->tuned)
-    if (t.key == key) {
-      t.tile = (int)bt;
-      t.anchor = ba;
-      found = true;
-    }
-  if (!found) ctx->tuned.push_back({key, (int)bt, ba});
+  remember_tuned(ctx, th, mode, cost_kind, work_all, (int)bt, ba);
   if (best_tile) *best_tile = (int32_t)bt;
   if (best_anchor) *best_anchor = ba;
   if (best_us) *best_us = best / 5.0 * 1e3;

@@ -1177,21 +1177,21 @@ constexpr int eval_min_waves() {
   return (COST == MU_COST_CHI2 && MODE == kModeCost && Sh::kFixed) ? 6 : 1;
 }
 
+// The workgroup's copy of the context's reciprocal table (chi^2 on integer
+// counts), 16 B per load and store.
+__device__ __forceinline__ void load_inv_table(double *inv_tab, const double *src) {
+  static_assert(kInvTab % 2 == 0, "table copied in pairs");
+  const double2 *s2 = reinterpret_cast<const double2 *>(src);
+  double2 *d2 = reinterpret_cast<double2 *>(inv_tab);
+  for (int i = threadIdx.x; i < kInvTab / 2; i += kBlock) d2[i] = s2[i];
+  __syncthreads();
+}
+
+// The work units (waves) of workgroup b of launch a.
 // TAB = 1: every count of the launch is an integer below kInvTab (the table
 // lookup needs neither clamp nor range test).
 template <int COST, int MODE, typename CT, typename Sh, int TAB>
-__global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
-  const int b = blockIdx.x;
-  constexpr bool kTable = COST == MU_COST_CHI2 && sizeof(CT) == 4 && MODE != kModeModel;
-  __shared__ __align__(16) double inv_tab[kTable ? kInvTab : 2];
-  if constexpr (kTable) {
-    // the context's table, 16 B per load and store
-    static_assert(kInvTab % 2 == 0, "table copied in pairs");
-    const double2 *src = reinterpret_cast<const double2 *>(a.inv_src);
-    double2 *dst = reinterpret_cast<double2 *>(inv_tab);
-    for (int i = threadIdx.x; i < kInvTab / 2; i += kBlock) dst[i] = src[i];
-    __syncthreads();
-  }
+__device__ __forceinline__ void eval_units(const LaunchArgs &a, int b, const double *inv_tab) {
   // each wave is one unit of work; no workgroup barrier after this point
   const int u = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + (int)(threadIdx.x / kWave));  // wave-uniform
   const int lane = threadIdx.x & (kWave - 1);
@@ -1256,6 +1256,35 @@ __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void ev
       ++v;
     }
   }
+}
+
+template <int COST, int MODE, typename CT>
+constexpr bool eval_table() {
+  return COST == MU_COST_CHI2 && sizeof(CT) == 4 && MODE != kModeModel;
+}
+
+template <int COST, int MODE, typename CT, typename Sh, int TAB>
+__global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
+  constexpr bool kTable = eval_table<COST, MODE, CT>();
+  __shared__ __align__(16) double inv_tab[kTable ? kInvTab : 2];
+  if constexpr (kTable) load_inv_table(inv_tab, a.inv_src);
+  eval_units<COST, MODE, CT, Sh, TAB>(a, blockIdx.x, inv_tab);
+}
+
+// A gradient pass and a cost pass over the same dataset and theory in one
+// launch: workgroups [0, n_grad_blocks) take the gradient launch's units, the
+// rest the cost launch's, so the gradient waves (few, latency-bound) run
+// beside the cost waves instead of before them. Four waves per SIMD: the
+// gradient body's registers.
+template <int COST, typename CT, typename Sh, int TAB>
+__global__ __launch_bounds__(kBlock, 4) void eval_grad_cost_kernel(LaunchArgs g, int n_grad_blocks, LaunchArgs c) {
+  constexpr bool kTable = eval_table<COST, kModeCost, CT>();
+  __shared__ __align__(16) double inv_tab[kTable ? kInvTab : 2];
+  if constexpr (kTable) load_inv_table(inv_tab, c.inv_src);
+  if ((int)blockIdx.x < n_grad_blocks)
+    eval_units<COST, kModeGrad, CT, Sh, TAB>(g, blockIdx.x, inv_tab);
+  else
+    eval_units<COST, kModeCost, CT, Sh, TAB>(c, blockIdx.x - n_grad_blocks, inv_tab);
 }
 
 // One workgroup per job: fixed-order merge of the job's slots.  It runs as
@@ -1339,6 +1368,49 @@ int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape) {
                              : occupancy_typed<MU_COST_CHI2, kModeCost>(count_f64, shape);
   return mode == kModeGrad ? occupancy_typed<MU_COST_POISSON, kModeGrad>(count_f64, shape)
                            : occupancy_typed<MU_COST_POISSON, kModeCost>(count_f64, shape);
+}
+
+namespace {
+
+template <int COST, typename Sh>
+hipError_t launch_grad_cost_shape(const LaunchArgs &g, const LaunchArgs &c, hipStream_t s) {
+  const int per = kBlock / kWave;
+  const int nbg = (g.n_units + per - 1) / per, nbc = (c.n_units + per - 1) / per;
+  dim3 grid(nbg + nbc), block(kBlock);
+  constexpr int kTab = COST == MU_COST_CHI2 ? 1 : 0;
+  if (kTab && c.counts_in_table && g.counts_in_table)
+    hipLaunchKernelGGL((eval_grad_cost_kernel<COST, uint32_t, Sh, kTab>), grid, block, 0, s, g, nbg, c);
+  else
+    hipLaunchKernelGGL((eval_grad_cost_kernel<COST, uint32_t, Sh, 0>), grid, block, 0, s, g, nbg, c);
+  return hipGetLastError();
+}
+
+template <int COST>
+hipError_t launch_grad_cost_typed(const LaunchArgs &g, const LaunchArgs &c, int shape, hipStream_t s) {
+  switch (shape) {
+    case kShapeExpCos: return launch_grad_cost_shape<COST, ShapeExpCos>(g, c, s);
+    case kShapeGaussCos: return launch_grad_cost_shape<COST, ShapeGaussCos>(g, c, s);
+    case kShapeStg: return launch_grad_cost_shape<COST, ShapeStg>(g, c, s);
+    case kShapeExpStg: return launch_grad_cost_shape<COST, ShapeExpStg>(g, c, s);
+    case kShapeExpCosStg: return launch_grad_cost_shape<COST, ShapeExpCosStg>(g, c, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace
+
+// chi^2 only: the likelihood's gradient body needs more registers than four
+// waves per SIMD leave (it would spill)
+bool eval_grad_cost_fused(int count_f64, int shape, int cost_kind) {
+  return !count_f64 && shape > kShapeGeneric && shape < kShapeCount && cost_kind == MU_COST_CHI2;
+}
+
+hipError_t launch_eval_grad_cost(const LaunchArgs &g, const LaunchArgs &c, int count_f64, int shape, hipStream_t s) {
+  if (!eval_grad_cost_fused(count_f64, shape, c.cost_kind) || g.cost_kind != c.cost_kind) return hipErrorNotSupported;
+  if (g.n_units <= 0 || c.n_units <= 0) return hipErrorInvalidValue;
+  if (g.anchor_every < 1 || g.anchor_every > 256 || c.anchor_every < 1 || c.anchor_every > 256)
+    return hipErrorInvalidValue;
+  return launch_grad_cost_typed<MU_COST_CHI2>(g, c, shape, s);
 }
 
 hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s) {

@@ -151,6 +151,12 @@ struct LaunchArgs {
 };
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);
+// A gradient launch g and a cost launch c of the same dataset and theory as
+// one launch, for the cases eval_grad_cost_fused accepts (chi^2, compiled
+// shapes, 32-bit counts; others take two launches); hipErrorNotSupported
+// otherwise.
+bool eval_grad_cost_fused(int count_f64, int shape, int cost_kind);
+hipError_t launch_eval_grad_cost(const LaunchArgs &g, const LaunchArgs &c, int count_f64, int shape, hipStream_t s);
 // Workgroups (of kBlock / kWave units each) of the evaluation kernel resident
 // per compute unit (0 if unknown).
 int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape);

@@ -374,6 +374,29 @@ def test_autotune_choice_keeps_parity(ctx):
         assert abs(got[v] - ref) <= REL * ref
 
 
+def test_autotune_set_replays_a_choice(ctx):
+    """Launches of the size a (tile, anchor) was recorded for keep parity
+    with it; out-of-range values are refused."""
+    _say("autotune_set")
+    cfg, counts = c1()
+    th, d = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    P = np.stack([perturbed(cfg["p_true"], 1e-3, 50 + v) for v in range(16)])
+    api.autotune_set(ctx, d, th, 16, 700, 8)
+    api.autotune_set(ctx, d, th, 16, 1000, 16, grad=True)
+    got = api.chi2_eval(ctx, d, th, P)
+    cg, g = api.chi2_grad(ctx, d, th, P)
+    for v in (0, 7, 15):
+        ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v])
+        assert abs(got[v] - ref) <= REL * ref
+        assert abs(cg[v] - ref) <= REL * ref
+        rg = model.grad(cfg["theory"], cfg["histos"], counts, P[v])
+        sc = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, P[v])
+        assert np.all(np.abs(g[v] - rg) <= REL * sc)
+    for bad in ((16, 63, 64), (16, 1 << 27, 64), (16, 1024, 0), (16, 1024, 257), (0, 1024, 64)):
+        with pytest.raises(api.A.MuError):
+            api.autotune_set(ctx, d, th, *bad)
+
+
 def test_kernel_timing_records_each_launch(ctx):
     """Event timing counts every evaluation and merge launch by kind and gives
     positive durations; disabling stops recording; enabling clears."""

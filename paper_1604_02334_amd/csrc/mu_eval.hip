@@ -739,15 +739,19 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 #pragma unroll
   for (int k = 0; k < kMaxT; ++k) coef[k] = k < n_terms ? bcast(th->coef[k], 0) : 0.0;
 
-  const int lane = tid & 63;
+  // Opaque to the optimiser: the lane masks of the lane-parallel prologue are
+  // then formed in each segment rather than hoisted out of the segment loop,
+  // where they stayed live across it in spilled scalar registers.
+  int lane = tid & 63;
+  asm volatile("" : "+v"(lane));
   // resolved scalars of this (vector, histogram): lane r of every wave
   // resolves scalar r, then each is broadcast to scalar registers
   double R[kRS];
   {
-    // the theory's functions f = F p + f0 (Sec. 4.2.1), once per segment: wave
-    // 0 forms each dot product lane-parallel with a fixed-order sum and
-    // shares them through LDS (a serial loop per scalar would wait on n_par
-    // loads)
+    // the theory's functions f = F p + f0 (Sec. 4.2.1), once per segment: the
+    // wave forms each dot product lane-parallel with a fixed-order sum and
+    // shares them through its LDS row (a serial loop per scalar would wait on
+    // n_par loads)
     __shared__ double f_all[kBlock / kWave][kFunStage];
     double *f_s = f_all[tid / kWave];  // this wave's copy
     const int n_fun = __builtin_amdgcn_readfirstlane(th->n_fun);

@@ -194,7 +194,11 @@ mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu
  * or finite-difference points; Sec. 4 and Table 1 count such evaluations).
  * Both passes run on the context's stream as one evaluation launch (chi^2,
  * compiled theory shapes, 32-bit counts; otherwise two launches) and share
- * one merge launch.  Results are bitwise those of the two separate calls.  Outputs:
+ * one merge launch.  The costs at params_cost are bitwise those of a separate
+ * mu_chi2_eval call.  In one launch the gradient pass takes longer bin ranges
+ * per wave than a mu_chi2_grad call of its own (unless mu_ctx_set_tile fixes
+ * them), so its cost and gradient equal that call's to rounding; with two
+ * launches, bitwise.  Outputs:
  * cost_grad [n_grad], grad [n_grad][n_par], cost [n_cost].  mem applies to
  * all parameter and output arrays.  Errors as mu_chi2_eval. */
 mu_status mu_chi2_eval_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,

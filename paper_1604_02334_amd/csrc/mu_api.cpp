@@ -914,15 +914,17 @@ struct Pending {
   int mode = 0, n_vec = 0, shape = 0, f64 = 0;
 };
 
-// Prepares (and, unless launch is false, enqueues) one evaluation launch.
+// Prepares (and, unless launch is false, enqueues) one evaluation launch;
+// w_force > 0 replaces the chosen bins per wave.
 static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp,
                              int32_t n_vec, double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s,
-                             DevBuf &partial, Pending &pend, bool launch = true) {
+                             DevBuf &partial, Pending &pend, bool launch = true, int64_t w_force = 0) {
   mu_status st;
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
   int anchor = ctx->anchor_every;
   const int64_t work = (int64_t)n_vec * d->total;
-  const int64_t W = ctx->pick_split(shape, mode, cost_kind, d->f64, work, &anchor);
+  int64_t W = ctx->pick_split(shape, mode, cost_kind, d->f64, work, &anchor);
+  if (w_force > 0) W = w_force;
   const int n_par = th->h.n_par;
   const int64_t n_units = (work + W - 1) / W;
   if (n_units + (int64_t)n_vec * d->n_histo > INT32_MAX) {
@@ -1082,13 +1084,26 @@ mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int 
   // for both: the gradient job's merge latency hides behind the cost jobs'
   // merges
   Pending pg_, pc_;
-  if ((st = eval_launch(ctx, d, th, cost_kind, dpg, n_grad, dcg, nullptr, dg, nullptr, kModeGrad, ctx->stream,
-                        ctx->partial_aux, pg_, false)) != MU_OK)
-    return st;
   if ((st = eval_launch(ctx, d, th, cost_kind, dpc, n_cost, dcc, nullptr, nullptr, nullptr, kModeCost, ctx->stream,
                         ctx->partial, pc_, false)) != MU_OK)
     return st;
-  if (eval_grad_cost_fused(pg_.f64, pg_.shape, cost_kind)) {
+  // In one launch the gradient waves run beside the cost waves, so longer
+  // gradient ranges cost no time there and leave fewer slots to merge: at
+  // least half a cost range, but at least 64 gradient waves (C2: 8192 bins
+  // per wave in place of the 1024-2048 a gradient launch of its own prefers).
+  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
+  const bool fused = eval_grad_cost_fused(d->f64, shape, cost_kind);
+  int64_t wg = 0;
+  if (fused && ctx->tile_bins == 0) {
+    int anchor_g = 0;
+    const int64_t work_g = (int64_t)n_grad * d->total;
+    const int64_t wg_own = ctx->pick_split(shape, kModeGrad, cost_kind, d->f64, work_g, &anchor_g);
+    wg = std::max<int64_t>(wg_own, std::min<int64_t>(pc_.a.split_w / 2, (work_g + 63) / 64));
+  }
+  if ((st = eval_launch(ctx, d, th, cost_kind, dpg, n_grad, dcg, nullptr, dg, nullptr, kModeGrad, ctx->stream,
+                        ctx->partial_aux, pg_, false, wg)) != MU_OK)
+    return st;
+  if (fused) {
     const int ti = ctx->time_begin(MU_TIME_EVAL_GRAD_COST, ctx->stream);
     e = launch_eval_grad_cost(pg_.a, pc_.a, pg_.f64, pg_.shape, ctx->stream);
     ctx->time_end(ti, ctx->stream);

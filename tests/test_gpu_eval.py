@@ -424,9 +424,11 @@ def test_kernel_timing_records_each_launch(ctx):
 
 @pytest.mark.parametrize("kind", ["chi2", "poisson"])
 def test_eval_grad_overlapped_matches_separate_calls(ctx, kind):
-    """The overlapped gradient + cost call equals the separate calls bit for
-    bit (same kernels and launch shapes), on host and device memory, and its
-    stencil costs match the oracle."""
+    """The combined gradient + cost call against the separate calls: the
+    stencil costs bit for bit (same launch shapes); the gradient pass, which
+    in one launch may take longer ranges per wave, to rounding for chi^2 and
+    bit for bit for the likelihood (two launches); host and device memory give
+    the same bits; the stencil costs and the gradient match the oracle."""
     import torch
     _say("eval_grad overlapped", kind)
     cfg, counts = c2()
@@ -436,9 +438,15 @@ def test_eval_grad_overlapped_matches_separate_calls(ctx, kind):
     cg, g, cc = api.chi2_eval_grad(ctx, d, th, p0, P, kind)
     sg, sgg = api.chi2_grad(ctx, d, th, p0, kind)
     sc = api.chi2_eval(ctx, d, th, P, kind)
-    np.testing.assert_array_equal(cg, sg)
-    np.testing.assert_array_equal(g, sgg)
     np.testing.assert_array_equal(cc, sc)
+    if kind == "poisson":
+        np.testing.assert_array_equal(cg, sg)
+        np.testing.assert_array_equal(g, sgg)
+    scale = model.grad_abs_scale(cfg["theory"], cfg["histos"], counts, p0, kind)
+    assert abs(cg[0] - sg[0]) <= _rounding_bound(cfg["theory"], cfg["histos"], counts, p0, kind)
+    assert np.all(np.abs(g[0] - sgg[0]) <= 1e-12 * scale)
+    ref_g = model.grad(cfg["theory"], cfg["histos"], counts, p0, kind)
+    assert np.all(np.abs(g[0] - ref_g) <= REL * scale)
     for v in (0, 8):
         ref = model.cost(cfg["theory"], cfg["histos"], counts, P[v], kind)
         assert abs(cc[v] - ref) <= REL * ref

@@ -460,6 +460,39 @@ def test_eval_grad_overlapped_matches_separate_calls(ctx, kind):
     np.testing.assert_array_equal(tcc.cpu().numpy(), cc)
 
 
+@pytest.mark.parametrize("shape", ["exp_cos", "gauss_cos", "stg", "exp_gkt"])
+def test_eval_grad_single_launch_every_compiled_shape(ctx, shape):
+    """The single evaluation launch of the gradient and cost passes for each
+    compiled shape (C2's is covered above): costs and gradient against the
+    oracle, the costs at the cost vectors bit for bit against a separate
+    call, and the gradient pass against a separate call to rounding. Uneven
+    fit range, so ranges end inside the last wave."""
+    _say("eval_grad single launch", shape)
+    rng = np.random.default_rng(23)
+    hs = [{"n_bins": 20000, "dt": 0.0005, "t0_bin": 0.0, "first": 3, "last": 19990, "map_row": 0}]
+    th_d, p = {"exp_cos": (synth.theory_exp_cos(), np.array([900.0, 3.0, 0.2, 0.8, 7.7, 0.3])),
+               "gauss_cos": (synth.theory_gauss_cos(), np.array([900.0, 3.0, 0.2, 0.9, 7.7, 0.3])),
+               "stg": (synth.theory_stg(), np.array([900.0, 3.0, 0.2, 0.95])),
+               "exp_gkt": (synth.theory_exp_gkt(), np.array([900.0, 3.0, 0.15, 0.8, 0.12, 0.4]))}[shape]
+    counts = counts_for(th_d, hs, p, rng)
+    th, d = _mk(ctx, th_d, hs, counts)
+    p0 = perturbed(p, 1e-2, 24)
+    P = np.stack([perturbed(p, 1e-2, 25 + v) for v in range(5)])
+    cg, g, cc = api.chi2_eval_grad(ctx, d, th, p0, P)
+    sg, sgg = api.chi2_grad(ctx, d, th, p0)
+    np.testing.assert_array_equal(cc, api.chi2_eval(ctx, d, th, P))
+    ref_c = model.cost(th_d, hs, counts, p0)
+    ref_g = model.grad(th_d, hs, counts, p0)
+    scale = model.grad_abs_scale(th_d, hs, counts, p0)
+    assert abs(cg[0] - ref_c) <= REL * ref_c
+    assert np.all(np.abs(g[0] - ref_g) <= REL * scale)
+    assert abs(cg[0] - sg[0]) <= _rounding_bound(th_d, hs, counts, p0)
+    assert np.all(np.abs(g[0] - sgg[0]) <= 1e-12 * scale)
+    for v in range(5):
+        ref = model.cost(th_d, hs, counts, P[v])
+        assert abs(cc[v] - ref) <= REL * ref
+
+
 def _stencil(p, rel=1e-4):
     rows = []
     for k in range(p.size):

@@ -228,7 +228,7 @@ mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
  * launch, the choice mu_autotune measured for the same theory shape, mode,
  * cost and size (to a power of two), else for single-dataset launches one
  * range per resident wave (at least 64 bins) and for batched launches
- * about sixteen waves per compute unit with tiles of 1024 .. 65536 bins.
+ * about 64 tiles (waves) per compute unit with tiles of 1024 .. 65536 bins.
  * Otherwise any value in [64, 2^26].  Results depend on it only through the
  * rounding order of the sums. */
 mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins);

@@ -7,6 +7,7 @@ Marshalling only: numpy arrays become host pointers (MU_MEM_HOST), CUDA
 
 from __future__ import annotations
 
+import array
 import ctypes as C
 
 import numpy as np
@@ -211,6 +212,7 @@ class Theory:
         h = C.c_void_p()
         _check(A.lib().mu_theory_create(ctx.h, C.byref(d), C.byref(h)), ctx.h, "mu_theory_create")
         self.h = h
+        self.addr = h.value  # the handle as an integer (batched calls pass arrays of them)
         self.ctx = ctx
         self.n_par = int(theory["n_par"])
         ctx._children.append(self)
@@ -219,6 +221,7 @@ class Theory:
         if self.h:
             _check(A.lib().mu_theory_destroy(self.h), None, "mu_theory_destroy")
             self.h = None
+            self.addr = 0
 
 
 class Data:
@@ -227,6 +230,7 @@ class Data:
         h = C.c_void_p()
         _check(A.lib().mu_data_create(ctx.h, arr, len(histos), C.byref(h)), ctx.h, "mu_data_create")
         self.h = h
+        self.addr = h.value  # the handle as an integer (batched calls pass arrays of them)
         self.ctx = ctx
         self.n_histo = len(histos)
         self.n_bins = int(A.lib().mu_data_bins(h))
@@ -237,6 +241,16 @@ class Data:
         if self.h:
             _check(A.lib().mu_data_destroy(self.h), None, "mu_data_destroy")
             self.h = None
+            self.addr = 0
+
+
+def handle_array(objs):
+    """(keep-alive buffer, pointer) of the objects' native handles, contiguous,
+    for the batched calls."""
+    a = array.array("Q", [o.addr for o in objs])
+    if 0 in a:
+        raise ValueError("a dataset or theory handle is closed")
+    return a, C.cast(a.buffer_info()[0], C.POINTER(C.c_void_p))
 
 
 def _cost_code(cost):
@@ -347,8 +361,8 @@ def chi2_batch(ctx, datas, theories, params, cost="chi2", grad=False):
     n = len(datas)
     if len(theories) != n:
         raise ValueError("need one theory per dataset")
-    dh = (C.c_void_p * n)(*[d.h.value for d in datas])
-    th = (C.c_void_p * n)(*[t.h.value for t in theories])
+    keep_d, dh = handle_array(datas)
+    keep_t, th = handle_array(theories)
     if _is_torch(params) and params.is_cuda:
         import torch
         p = params.detach().to(torch.float64).contiguous()
@@ -446,8 +460,8 @@ def fit_batch(ctx, datas, theories, start, cost="chi2", fixed=None, analytic_gra
     out = np.empty((n, ld))
     cov = np.empty((n, ld, ld)) if want_cov else None
     res = (A.mu_fit_result * n)()
-    dh = (C.c_void_p * n)(*[d.h.value for d in datas])
-    th = (C.c_void_p * n)(*[t.h.value for t in theories])
+    keep_d, dh = handle_array(datas)
+    keep_t, th = handle_array(theories)
     _check(L.mu_fit_batch(ctx.h, n, dh, th, _cost_code(cost), ld, s.ctypes.data, C.byref(o), out.ctypes.data,
                           cov.ctypes.data if want_cov else None, res), ctx.h, "mu_fit_batch")
     rs = [{"cost": r.cost, "edm": r.edm, "n_iter": r.n_iter, "n_fcn": r.n_fcn, "n_grad": r.n_grad,

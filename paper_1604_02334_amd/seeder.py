@@ -7,7 +7,7 @@ import ctypes as C
 import numpy as np
 
 from . import _abi as A
-from .api import _check
+from .api import _check, handle_array
 
 _DECL = {
     "mu_seeder_param_count": (C.c_int64, []),
@@ -128,7 +128,7 @@ class Seeder:
 
     def infer(self, datas):
         n = len(datas)
-        dh = (C.c_void_p * n)(*[d.h.value for d in datas])
+        keep_d, dh = handle_array(datas)
         start = np.empty((n, 6))
         ok = np.empty(n, dtype=np.uint8)
         _check(_lib().mu_seed_infer(self.ctx.h, self.h, n, dh, start.ctypes.data, ok.ctypes.data), self.ctx.h,

@@ -107,3 +107,21 @@ def test_histogram_validation_errors():
     # a bad value outside the fit range is not read
     assert api.histo_check([dict(h, first=4)], [bad])[0] == A.MU_OK
     assert api.histo_check([], [])[0] == A.MU_E_ARG
+
+
+def test_handle_array_is_contiguous_and_refuses_closed_handles():
+    """The batched calls' handle arrays: the integer handles in order, one
+    pointer to them, and an error (not a null handle passed on) for a closed
+    dataset or theory."""
+    from paper_1604_02334_amd import api
+
+    class Handle:
+        def __init__(self, addr):
+            self.addr = addr
+
+    objs = [Handle(4096 * (i + 1)) for i in range(5)]
+    keep, ptr = api.handle_array(objs)
+    assert [ptr[i] for i in range(5)] == [o.addr for o in objs]
+    objs[3].addr = 0
+    with pytest.raises(ValueError):
+        api.handle_array(objs)

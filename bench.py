@@ -188,6 +188,26 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     for _ in range(5):
         api.chi2_batch(ctx, datas, ths, start)
     t_pass = (time.perf_counter() - t0) / 5
+    # the same with parameters and costs resident on the device, and the
+    # kernels' own time from the library's events
+    import torch
+    p_dev = torch.tensor(start, device="cuda")
+    with torch.cuda.stream(ctx.torch_stream):
+        api.chi2_batch(ctx, datas, ths, p_dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            api.chi2_batch(ctx, datas, ths, p_dev)
+        torch.cuda.synchronize()
+        t_dev = (time.perf_counter() - t0) / 5
+        ctx.timing(True)
+        for _ in range(5):
+            api.chi2_batch(ctx, datas, ths, p_dev)
+        torch.cuda.synchronize()
+        ctx.timing(False)
+    n_k, ms_k = ctx.timing_read("cost")
+    n_m, ms_m = ctx.timing_read("merge")
+    t_kern = (ms_k + ms_m) / 5 * 1e-3
     _log(f"c4: {n_sets} datasets, {bins} bins; batched fits")
     t0 = time.perf_counter()
     pb, covb, rb = api.fit_batch(ctx, datas, ths, start)
@@ -224,6 +244,11 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     return {"datasets": n_sets, "bins": int(bins),
             "single_pass": {"ms": round(t_pass * 1e3, 3), "gbin_s": round(bins / t_pass / 1e9, 1),
                             "note": "host parameters and results, one launch per theory shape + merge"},
+            "single_pass_device": {"ms": round(t_dev * 1e3, 3), "gbin_s": round(bins / t_dev / 1e9, 1),
+                                   "kernels_ms": round(t_kern * 1e3, 3),
+                                   "kernels_gbin_s": round(bins / t_kern / 1e9, 1),
+                                   "launches": n_k // 5,
+                                   "note": "parameters and costs on the device; kernels = evaluation + merge"},
             "batched": {"fits": n_sets, "seconds": round(tb, 3), "fits_per_s": round(n_sets / tb, 2),
                         "converged": int(sum(r["status"] == 0 for r in rb)),
                         "unconverged_ill_conditioned": ill,

@@ -31,6 +31,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 
 #include "mu_internal.h"
@@ -105,6 +107,20 @@ using ShapeGaussCos = ShapeFixed<1, 2, MU_SG, MU_TF, 0, 0, 0>;
 using ShapeStg = ShapeFixed<1, 1, MU_STG, 0, 0, 0, 0>;
 using ShapeExpStg = ShapeFixed<2, 1, MU_SE, 0, 1, MU_STG, 0>;
 using ShapeExpCosStg = ShapeFixed<2, 2, MU_SE, MU_TF, 1, MU_STG, 0>;
+
+// Whether a compiled shape has a rotation factor.
+template <typename Sh>
+constexpr bool shape_has_tf() {
+  if constexpr (!Sh::kFixed) {
+    return false;
+  } else {
+    TStruct ts{};
+    for (int kt = 0; kt < Sh::nt(ts); ++kt)
+      for (int f = 0; f < Sh::nf(ts, kt); ++f)
+        if (Sh::prim(ts, kt, f) == MU_TF) return true;
+    return false;
+  }
+}
 
 // Exponentials an anchor of a compiled shape needs: the lifetime, one per
 // exponential factor, two per Gaussian factor (state and ratio).
@@ -860,6 +876,35 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     for (int s = 0; s < kSlots; ++s) su[s] = R[kArg0 + 2 * s] * h;
   }
 
+  // Cost and model passes of compiled shapes with a rotation: when every
+  // rotation turns by at least 1/16 rad-sine per lane step, its real part
+  // alone follows x_{k+1} = a x_k - b x_{k-1} (a = 2 rho cos(theta),
+  // b = rho^2; rho = 1 exactly for a rotation that is not scaled), which
+  // needs neither the imaginary part nor a complex product. Its rounding grows
+  // like k min(k, 1 / sin(theta)) eps/2 between anchors (below 3e-13 of the
+  // term at 256 steps and this bound), against k eps for the rotation.
+  constexpr bool kChebShape = kScaled && shape_has_tf<Sh>();
+  double cheb_a[kSlots], cheb_b[kSlots], cheb_ib[kSlots];
+  bool cheb_ok = false;
+  if constexpr (kChebShape) {
+    cheb_ok = true;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int kt = s / kMaxFT, f = s % kMaxFT;
+      cheb_a[s] = cheb_b[s] = cheb_ib[s] = 1.0;
+      if (kt < n_terms && f < Sh::nf(ts, kt) && Sh::prim(ts, kt, f) == MU_TF) {
+        const bool unit = f > 0 && !(f == 1 && Sh::fold(ts, kt));  // the step constants are cos and sin
+        cheb_a[s] = 2.0 * c0[s];
+        if (!unit) {
+          cheb_b[s] = fma(c0[s], c0[s], c1[s] * c1[s]);
+          cheb_ib[s] = 1.0 / cheb_b[s];
+        }
+        cheb_ok = cheb_ok && c1[s] * c1[s] >= cheb_b[s] * (1.0 / 256.0);
+      }
+    }
+    cheb_ok = __builtin_amdgcn_readfirstlane((int)cheb_ok) != 0;
+  }
+
   // per-lane states
   double E = 0.0;
   double s0[kSlots], s1[kSlots], u[kSlots];
@@ -905,8 +950,10 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     if constexpr (kTable) return inv_count<TAB>((uint32_t)raw, x, S.inv_tab);
     return 0.0;
   };
-  // x_cur: the stored count widened (8 d for integer storage)
-  auto bin_step = [&](int k, double x_cur, double iv) {
+  // x_cur: the stored count widened (8 d for integer storage); cheb_tag
+  // selects the rotations' real-part recurrence (see above)
+  auto bin_step = [&](auto cheb_tag, int k, double x_cur, double iv) {
+    constexpr bool kCheb = decltype(cheb_tag)::value;
     const int64_t idx = idx0 + (int64_t)k * kWave;
       if constexpr (kScaled) {
         double acc = E + nbkg;
@@ -1021,13 +1068,21 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
       for (int s = 0; s < kSlots; ++s) {
         const int kt = s / kMaxFT, f = s % kMaxFT;
         if (kt < n_terms && f < Sh::nf(ts, kt) && !(kScaled && f == 0 && Sh::fold(ts, kt))) {
-          advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+          if (kCheb && Sh::prim(ts, kt, f) == MU_TF) {
+            const double nx = fma(cheb_a[s], s0[s], -(cheb_b[s] * s1[s]));
+            s1[s] = s0[s];
+            s0[s] = nx;
+          } else {
+            advance(Sh::prim(ts, kt, f), c0[s], c1[s], s0[s], s1[s]);
+          }
           if (kScaled && Sh::prim(ts, kt, f) == MU_STG) u[s] += su[s];
         }
       }
     if constexpr (!kScaled) t += h;
   };
 
+  auto run = [&](auto cheb_tag) {
+  constexpr bool kCheb = decltype(cheb_tag)::value;
   for (int k0 = 0; k0 < n_max; k0 += every) {
     // exact re-evaluation (anchor) at the first step of the segment
     t = fma((double)k0, h, t_first);
@@ -1097,6 +1152,8 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
             s0[s] *= s0[s - 1];
             s1[s] *= s0[s - 1];
           }
+          // real-part recurrence: (x_k, x_{k-1}) = (Re z, Re(z / q))
+          if (kCheb && p == MU_TF) s1[s] = fma(s0[s], c0[s], s1[s] * c1[s]) * cheb_ib[s];
         }
       }
     }
@@ -1115,7 +1172,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
           // scheduler would otherwise sink it towards the end of the loop)
           __builtin_amdgcn_sched_barrier(0);
         }
-        bin_step(k + i, x, iv);
+        bin_step(cheb_tag, k + i, x, iv);
       }
     }
     // only the last segment has a tail: under kPrefetch uniform steps, then
@@ -1123,8 +1180,18 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     if (k < k0 + every) {
 #pragma unroll
       for (int i = 0; i < kPrefetch; ++i)
-        if (k + i < n_full || (extra && k + i == n_full)) bin_step(k + i, (double)dq[i], inv_of(dq[i], (double)dq[i]));
+        if (k + i < n_full || (extra && k + i == n_full))
+          bin_step(cheb_tag, k + i, (double)dq[i], inv_of(dq[i], (double)dq[i]));
     }
+  }
+  };
+  if constexpr (kChebShape) {
+    if (cheb_ok)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
+  } else {
+    run(std::false_type{});
   }
   if constexpr (MODE == kModeModel) return;
 

@@ -493,6 +493,37 @@ def test_eval_grad_single_launch_every_compiled_shape(ctx, shape):
         assert abs(cc[v] - ref) <= REL * ref
 
 
+@pytest.mark.parametrize("shape", ["exp_cos", "gauss_cos"])
+def test_rotation_recurrences_across_the_switch(ctx, shape):
+    """The cost and model passes follow a rotation's real part by a three-term
+    recurrence when it turns by at least 1/16 (sine) per lane step, else by the
+    complex rotation. Precession frequencies on both sides of that switch and
+    far above it, at the longest anchor interval (256 steps): costs and model
+    values against the oracle, and the cost pass against the gradient pass
+    (which always rotates) to rounding. Lane step here: 64 x 0.0005 us, so
+    sin(theta) = 1/16 at nu = 0.311 MHz."""
+    _say("rotation recurrences", shape)
+    rng = np.random.default_rng(26)
+    hs = [{"n_bins": 40000, "dt": 0.0005, "t0_bin": 0.0, "first": 0, "last": 39999, "map_row": 0}]
+    th_d = synth.theory_exp_cos() if shape == "exp_cos" else synth.theory_gauss_cos()
+    try:
+        ctx.anchor = 256
+        for nu in (0.05, 0.29, 0.33, 3.0, 40.0):
+            p = np.array([2000.0, 4.0, 0.25, 0.4, nu, 0.7])
+            counts = counts_for(th_d, hs, p, rng)
+            th, d = _mk(ctx, th_d, hs, counts)
+            got = api.chi2_eval(ctx, d, th, p)[0]
+            ref = model.cost(th_d, hs, counts, p)
+            assert abs(got - ref) <= REL * ref, (nu, got, ref)
+            cg, _ = api.chi2_grad(ctx, d, th, p)
+            assert abs(cg[0] - got) <= _rounding_bound(th_d, hs, counts, p), nu
+            m = api.model_eval(ctx, d, th, p)
+            ref_m = model.model(th_d, hs[0], p)
+            np.testing.assert_allclose(m, ref_m, rtol=1e-12, atol=0)
+    finally:
+        ctx.anchor = 0
+
+
 def _stencil(p, rel=1e-4):
     rows = []
     for k in range(p.size):

@@ -43,18 +43,19 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_FP64_TOPS = 39.3
 # Per bin of the 16-detector cost pass as the kernel computes it (lifetime,
 # N0 and term weights folded into the first factor of each term, the
-# exponential of the se * tf term into its complex rotation state; reciprocal
-# variance from the workgroup's table):
-#   model: lifetime 1 mul, decaying rotation 2 mul + 2 fma, Gaussian 2 mul,
-#   sigma t 1 add, 1 - (sigma t)^2 1 fma, background and the two terms
-#   2 add + 1 fma                               -> 12 instructions, 16 flops
+# exponential of the se * tf term into its rotation; that rotation turns by
+# more than 1/16 per lane step, so its real part follows the three-term
+# recurrence; reciprocal variance from the workgroup's table):
+#   model: lifetime 1 mul, rotation's real part 1 mul + 1 fma, Gaussian
+#   2 mul, sigma t 1 add, 1 - (sigma t)^2 1 fma, background and the two terms
+#   2 add + 1 fma                               -> 10 instructions, 13 flops
 #   chi^2: d - N (one fma with the decode of the stored 8 d), times 1/v,
 #   fused square-accumulate                     ->  3 instructions,  4 flops
 #   plus widening the stored 8 d (it is also the table entry's byte offset;
 #   every count of this data set is below the table size, so no clamp and no
 #   range test)                                 ->  1 instruction,   0 flops
-FLOPS_PER_BIN_CHI2 = 20   # FMA = 2
-VALU_PER_BIN_CHI2 = 16    # instructions per bin of the per-bin loop
+FLOPS_PER_BIN_CHI2 = 17   # FMA = 2
+VALU_PER_BIN_CHI2 = 14    # instructions per bin of the per-bin loop
 # Per bin of the gradient pass (N, dN/dR for the 30 resolved scalars of the
 # shape, chi^2 and r dN/dR accumulated), from the same loop's ISA: 56 fma,
 # 120 mul, 24 add per four bins, and 52 FP64 instructions per bin.

@@ -1,31 +1,35 @@
 // Fused theory-evaluate-and-reduce kernels for gfx950.
 //
-// One workgroup (256 lanes, four wave64s) takes one tile: a run of consecutive
-// fit-range bins of one histogram for one parameter vector.  Lane l of the
-// tile reads bins l, l + 256, l + 512, ... so that every step of the
-// workgroup streams 256 consecutive counts (1 KiB of FP32) from memory.
+// The unit of work is one wave (64 lanes; four waves per workgroup share its
+// reciprocal table): a range of consecutive fit-range bins, evaluated as the
+// (parameter vector, histogram) segments it crosses.  Lane l of a segment reads
+// bins l, l + 64, l + 128, ... so that every step of the wave streams 64
+// consecutive 32-bit counts (256 B) from memory.
 //
 // Per bin the lane evaluates the theory program (Listings 2-3), the histogram
 // model (Eq. 1) and the cost term (Eq. 2 or Eq. 3); in gradient mode it also
 // accumulates r dN/dR for every resolved scalar R (r = d term / dN).
 //
 // Evaluation by anchored recurrences.  The time grid is uniform, so along one
-// lane (time step h = 256 dt) every primitive except the stretched
+// lane (time step h = 64 dt) every primitive except the stretched
 // exponential obeys an exact multiplicative recurrence:
 //   e^(-t/tau), se:  v(t+h) = v(t) e^(-lambda h)                (geometric)
 //   sg, stg:         g(t+h) = g(t) q(t),  q(t+h) = q(t) e^(-(sigma h)^2)
 //                    with q(t) = e^(-sigma^2 h (t + h/2))       (second order)
 //   tf:              (cos, sin)(theta + omega h) = rotation by omega h
+//                    (cost and model passes, sin(omega h) >= 1/16: the real
+//                    part alone by a three-term recurrence)
 // Each lane evaluates the exact values at its first bin (the anchor) and
 // re-anchors every `anchor_every` steps; the step constants are uniform and
-// computed once per workgroup.  Rounding drift grows like k eps for the
-// geometric and rotation sequences and k^2 eps / 2 for the Gaussian one, so
-// at most 64 steps between anchors keep every factor within ~5e-13 relative of
-// its directly evaluated value.  ge (beta free) is evaluated directly.
+// computed once per segment.  Rounding drift grows like k eps for the
+// geometric and rotation sequences, k min(k, 1/sin(omega h)) eps / 2 for the
+// three-term one and k^2 eps / 2 for the Gaussian one, so 256 steps between
+// anchors keep every factor within ~4e-12 relative of its directly evaluated
+// value.  ge (beta free) is evaluated directly.
 //
-// Reduction: per lane a plain FP64 sum over its <= 256 bins, then compensated
-// (TwoSum) merges across the wave, the workgroup and the tiles of the job.
-// Each tile writes its own slot; a second, one-workgroup-per-job kernel merges
+// Reduction: per lane a plain FP64 sum over its bins, then compensated
+// (TwoSum) merges across the wave and across the segments of the job.  Each
+// segment writes its own slot; a second, one-workgroup-per-job kernel merges
 // the job's slots in a fixed order, so results are bitwise reproducible and
 // no atomics or device-scope fences are used.
 
@@ -61,7 +65,7 @@ struct D2 {
 // of each term and their primitives, so the compiler keeps only the states,
 // step constants and accumulators that shape needs; the generic shape reads
 // them from the theory program at run time.
-// Structure of a theory program held in scalar registers by every workgroup.
+// Structure of a theory program held in scalar registers by every wave.
 struct TStruct {
   int nt;
   int nf[kMaxT];
@@ -235,7 +239,7 @@ __device__ __forceinline__ DevHisto uni(DevHisto x) {
   return x;
 }
 
-// Out-of-line transcendentals: they run at anchors and in the workgroup
+// Out-of-line transcendentals: they run at anchors and in the segment
 // prologue, and one copy each keeps the kernels small.
 __device__ __attribute__((noinline)) double x_exp(double x) { return exp(x); }
 // cos and sin of pi x: the phase is reduced in half-cycles, exactly
@@ -540,7 +544,7 @@ __device__ double sum_slot_pairs(const double *P, int k0, int k1) {
 
 // Merge the tile slots of job J in a fixed order and write its outputs.
 // Slots of one job: per histogram a contiguous range, and the span of all of
-// them (tile launch: the job's tile table; split launch: workgroup + histogram
+// them (tile launch: the job's tile table; split launch: unit + histogram
 // index of each segment).
 struct SlotMap {
   const double *P;
@@ -720,7 +724,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
 
 // What one segment needs: bins [begin, begin + n) of one histogram's fit
 // range (first bin `first` of the histogram, counts from `off` in the
-// concatenated counts), evaluated for the parameter vector p; the workgroup's
+// concatenated counts), evaluated for the parameter vector p; the wave's
 // cost (and gradient) partials go to its slot.
 struct SegIn {
   const double *inv_tab;  // chi^2 on integer counts: 1 / max(d, 1) for d < kInvTab (LDS)
@@ -918,7 +922,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 
   const int64_t n_first = S.first + S.begin + lane;  // this lane's first bin
   const double t_first = ((double)n_first - S.t0_bin) * S.dt;
-  // every lane has n_full bins; lanes below S.n % 256 have one more
+  // every lane has n_full bins; lanes below S.n % 64 have one more
   const int seg_n = __builtin_amdgcn_readfirstlane(S.n);  // wave-uniform: scalar loop control
   const int n_full = seg_n / kWave;
   const bool extra = lane < (seg_n % kWave);

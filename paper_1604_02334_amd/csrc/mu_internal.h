@@ -17,7 +17,7 @@ constexpr int kMaxFT = MU_MAX_FACTORS_PER_TERM;
 constexpr int kArg0 = 2 + kMaxT;
 constexpr int kRS = kArg0 + kMaxT * kMaxFT * 2;  // 30
 // Lane steps between a count's load and its use; the counts buffer is padded
-// by this many steps of 256 values.
+// by kPrefetch x kBlock values, more than this many lane steps (of 64 values).
 constexpr int kPrefetch = 4;
 // Entries of the per-workgroup table of 1 / max(d, 1) for integer counts
 // d < kInvTab (chi^2 kernels; FP64, 24 KiB of LDS: six workgroups of the

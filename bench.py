@@ -57,10 +57,10 @@ PEAK_FP64_TOPS = 39.3
 FLOPS_PER_BIN_CHI2 = 17   # FMA = 2
 VALU_PER_BIN_CHI2 = 14    # instructions per bin of the per-bin loop
 # Per bin of the gradient pass (N, dN/dR for the 30 resolved scalars of the
-# shape, chi^2 and r dN/dR accumulated), from the same loop's ISA: 56 fma,
-# 120 mul, 24 add per four bins, and 52 FP64 instructions per bin.
-FLOPS_PER_BIN_GRAD = 64
-VALU_PER_BIN_GRAD = 52
+# shape, chi^2 and r dN/dR accumulated), from the same loop's ISA: 64 fma,
+# 108 mul, 12 add per four bins, and 47 FP64 instructions per bin.
+FLOPS_PER_BIN_GRAD = 62
+VALU_PER_BIN_GRAD = 47
 BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
 COUNTERS = os.path.join(ROOT, "profiles", "eval_grad_cost_kernel_c2_step_counters.md")
 KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h"]

@@ -793,6 +793,10 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     for (int r = 0; r < kRS; ++r) R[r] = bcast(mine, r);
   }
   const double n0 = R[0], nbkg = R[1];
+  // term weights coef_k amp_k (uniform)
+  double gw[kMaxT];
+#pragma unroll
+  for (int k = 0; k < kMaxT; ++k) gw[k] = k < n_terms ? coef[k] * R[2 + k] : 0.0;
   const double h = S.dt * (double)kWave;  // lane step
 
   // uniform step constants, one transcendental per lane of every wave, then
@@ -1017,7 +1021,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
       } else {
         double val[kSlots], d0[kSlots], d1[kSlots];
         double tprod[kMaxT];
-        double A = 0.0;
+        double onepA = 1.0;  // 1 + A
 #pragma unroll
         for (int kt = 0; kt < kMaxT; ++kt) {
           tprod[kt] = 1.0;
@@ -1033,23 +1037,34 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
                 tprod[kt] *= val[s];
               }
             }
-            A = fma(coef[kt] * R[2 + kt], tprod[kt], A);
+            onepA = fma(gw[kt], tprod[kt], onepA);
           }
         }
-        const double N = fma(n0 * E, 1.0 + A, nbkg);
-        double dN;
-        const double d_cur = kIntData ? x_cur * kCountUnscale : x_cur;
-        lane_cost += cost_term<COST, true, kIntData>(d_cur, N, iv, dN);
-        const double rE = dN * E;    // r dN/dN0 = rE (1 + A)
-        const double rNE = rE * n0;  // r N0 e^(-t/tau)
-        g[0] = fma(rE, 1.0 + A, g[0]);
-        g[1] += dN;
+        const double n0E = n0 * E;
+        const double N = fma(n0E, onepA, nbkg);
+        // hN = -(1/2) d term / dN; the sums below carry that factor and are
+        // scaled by -2 once after the segment
+        double hN;
+        if constexpr (COST == MU_COST_CHI2 && kIntData) {
+          const double diff = fma(x_cur, kCountUnscale, -N);
+          const double w = diff * iv;
+          lane_cost = fma(diff, w, lane_cost);
+          hN = w;
+        } else {
+          double dN;
+          const double d_cur = kIntData ? x_cur * kCountUnscale : x_cur;
+          lane_cost += cost_term<COST, true, kIntData>(d_cur, N, iv, dN);
+          hN = -0.5 * dN;
+        }
+        const double hE = hN * E;     // dN/dN0 = E (1 + A)
+        const double hNE = hN * n0E;  // with N0 e^(-t/tau)
+        g[0] = fma(hE, onepA, g[0]);
+        g[1] += hN;
 #pragma unroll
         for (int kt = 0; kt < kMaxT; ++kt) {
           if (kt < n_terms) {
-            const double ck = coef[kt];
-            g[2 + kt] = fma(rNE * ck, tprod[kt], g[2 + kt]);
-            const double ca = rNE * ck * R[2 + kt];
+            g[2 + kt] = fma(hNE * coef[kt], tprod[kt], g[2 + kt]);
+            const double ca = hNE * gw[kt];
 #pragma unroll
             for (int f = 0; f < kMaxFT; ++f) {
               const int s = kt * kMaxFT + f;
@@ -1216,7 +1231,8 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         used = kt < n_terms && f < Sh::nf(ts, kt) && ai < prim_nargs(Sh::prim(ts, kt, f));
       }
       double sr = 0.0;
-      if (used && (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN)) sr = wave_sum(g[r]);
+      // the lanes summed -(1/2) r dN/dR (exact scaling by a power of two)
+      if (used && (th->rref[r].kind == MU_REF_PAR || th->rref[r].kind == MU_REF_FUN)) sr = -2.0 * wave_sum(g[r]);
       if (lane == 0) slot[2 + r] = sr;
     }
   }

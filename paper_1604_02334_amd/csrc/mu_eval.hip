@@ -181,27 +181,15 @@ __device__ __forceinline__ double dpp_d(double v) {
 // Compensated sum over the wave, the same in every lane. Within a row of 16
 // lanes: partner lanes 1 apart, then 2 (quad swaps), then the other half of
 // the group of 8 (half mirror), then of the row (mirror); after each step all
-// lanes of a group hold the same pair, and the pair holding the lower lanes
-// is always the left operand, so both partners compute identical results.
-// The four row results are then combined in a fixed order.
+// lanes of a group hold the same pair. pair_add is symmetric to the bit (the
+// sum and the TwoSum error, which is exact, do not depend on the operand
+// order; the corrections are added commutatively first), so partners need no
+// ordering. The four row results are then combined in a fixed order.
 __device__ __forceinline__ Pair wave_pair_sum(Pair p) {
-  const int lane = threadIdx.x & 63;
-  {
-    const Pair o{dpp_d<0xB1>(p.s), dpp_d<0xB1>(p.c)};
-    p = (lane & 1) ? pair_add(o, p) : pair_add(p, o);
-  }
-  {
-    const Pair o{dpp_d<0x4E>(p.s), dpp_d<0x4E>(p.c)};
-    p = (lane & 2) ? pair_add(o, p) : pair_add(p, o);
-  }
-  {
-    const Pair o{dpp_d<0x141>(p.s), dpp_d<0x141>(p.c)};
-    p = (lane & 4) ? pair_add(o, p) : pair_add(p, o);
-  }
-  {
-    const Pair o{dpp_d<0x140>(p.s), dpp_d<0x140>(p.c)};
-    p = (lane & 8) ? pair_add(o, p) : pair_add(p, o);
-  }
+  p = pair_add(p, Pair{dpp_d<0xB1>(p.s), dpp_d<0xB1>(p.c)});
+  p = pair_add(p, Pair{dpp_d<0x4E>(p.s), dpp_d<0x4E>(p.c)});
+  p = pair_add(p, Pair{dpp_d<0x141>(p.s), dpp_d<0x141>(p.c)});
+  p = pair_add(p, Pair{dpp_d<0x140>(p.s), dpp_d<0x140>(p.c)});
   const Pair r0{bcast(p.s, 0), bcast(p.c, 0)}, r1{bcast(p.s, 16), bcast(p.c, 16)};
   const Pair r2{bcast(p.s, 32), bcast(p.c, 32)}, r3{bcast(p.s, 48), bcast(p.c, 48)};
   return pair_add(pair_add(r0, r1), pair_add(r2, r3));

@@ -506,7 +506,7 @@ def main():
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "the benchmark runs on one GPU: the evaluation path has no multi-GPU sharding (only a design for it)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -16,7 +16,8 @@ definitions:
 Modules: ``model`` (cost and analytic gradient), ``scalar`` (pure-Python
 cross-check for tiny inputs), ``fit`` (reference minimiser), ``seeder``
 (reference network with BF16 rounding), ``philox`` (counter-based generator
-from its published definition), ``gen`` (the seeder's histogram generator).
+from its published definition; the seeder's parameter draws and expected
+rebinned counts live in ``seeder``).
 
 Every function states the passage it follows.  Pins that tie each function to
 something other than itself live in ``tests/test_oracle_*.py``.

@@ -206,10 +206,16 @@ mu_status mu_chi2_eval_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *t
                             int32_t n_cost, unsigned mem, double *cost_grad, double *grad, double *cost);
 
 /* Batched evaluation of n_jobs independent (dataset, theory, parameter
- * vector) jobs of uneven sizes in one launch.  params: [n_jobs][ld] with
- * ld >= every theory's n_par (each job reads its first n_par entries).
- * cost: [n_jobs]; grad: [n_jobs][ld] or NULL (entries past a job's n_par are
- * left untouched).  Data and theories may repeat across jobs. */
+ * vector) jobs of uneven sizes (Sec. 4: many cost evaluations per fit, here
+ * across fits and datasets).  The fit ranges of all jobs whose theory matches
+ * a compiled shape are concatenated and cut into equal ranges, one per
+ * 64-lane wave, in ONE evaluation launch in which every segment runs its own
+ * job's compiled shape; jobs of other theories (or FP64 counts) take one more
+ * launch of the interpreted kernel; one merge launch follows.  params:
+ * [n_jobs][ld] with ld >= every theory's n_par (each job reads its first
+ * n_par entries).  cost: [n_jobs]; grad: [n_jobs][ld] or NULL (entries past a
+ * job's n_par are left untouched).  Data and theories may repeat across jobs.
+ * All datasets must share one count storage (MU_E_UNSUPPORTED otherwise). */
 mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data,
                         const mu_theory *const *th, mu_cost cost_kind, int32_t ld,
                         const double *params, unsigned mem, double *cost, double *grad);
@@ -224,13 +230,15 @@ mu_status mu_model_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
  * Single-dataset launches (mu_chi2_eval, mu_chi2_grad, mu_model_eval) cut the
  * n_vec x bins work into equal ranges of this many bins, one per wave,
  * across histogram and vector boundaries; batched launches (mu_chi2_batch,
- * the fitter) cut each histogram into tiles of this size.  0 (default): per
- * launch, the choice mu_autotune measured for the same theory shape, mode,
- * cost and size (to a power of two), else for single-dataset launches one
- * range per resident wave (at least 64 bins) and for batched launches
- * about 64 tiles (waves) per compute unit with tiles of 1024 .. 65536 bins.
- * Otherwise any value in [64, 2^26].  Results depend on it only through the
- * rounding order of the sums. */
+ * the fitter) cut the concatenated fit ranges of their jobs the same way,
+ * across histogram and job boundaries.  0 (default): per launch, the choice
+ * mu_autotune (single-dataset) or mu_autotune_batch (batched) measured for
+ * the same kind of launch, theory shape, mode, cost and size (to a power of
+ * two), else one range per resident wave (at least 64 bins).
+ * Otherwise any value in [64, 2^26]; gradient passes cut their ranges at
+ * 2^20 bins per wave (each lane then sums at most 2^14 terms plainly; cost
+ * passes fold their per-lane sums by TwoSum at every anchor).  Results depend
+ * on it only through the rounding order of the sums. */
 mu_status mu_ctx_set_tile(mu_ctx *ctx, int32_t tile_bins);
 int32_t mu_ctx_get_tile(const mu_ctx *ctx);
 
@@ -291,6 +299,37 @@ mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_
 mu_status mu_autotune_set(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
                           int32_t n_vec, int32_t grad, int32_t tile_bins, int32_t anchor_every);
 
+/* The batched counterpart of mu_autotune (the paper plans auto-tuning of
+ * its kernels, Secs. 3 and 6): runs the jobs of a mu_chi2_batch call (cost,
+ * or cost and gradient when grad != 0) at several bins-per-wave values (1, 2,
+ * 3, 4, 6 or 8 ranges per resident wave, powers of two from 1024 to 65536)
+ * and anchor intervals 32 .. 256, keeps candidates whose costs agree with the
+ * first to 1e-12 relative, and remembers the fastest for later batched
+ * launches of the same mode, cost and size (to a power of two) while the
+ * tile size is 0.  Outputs as mu_autotune (any may be NULL). */
+mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,
+                            mu_cost cost_kind, int32_t ld, const double *params, unsigned mem, int32_t grad,
+                            int32_t *best_tile, int32_t *best_anchor, double *best_us);
+
+/* Tuning cache file: the choices mu_autotune, mu_autotune_batch and
+ * mu_autotune_set remembered on this context, as text:
+ *   mu-autotune 1
+ *   arch <device architecture, e.g. gfx950:sramecc+:xnack->
+ *   <shape> <mode> <cost> <kind> <log2 size> <bins per wave> <anchor>   (one line each)
+ * shape 0 interpreted, 1..5 compiled shapes, 6 batched launch of compiled
+ * shapes; mode 0 cost, 1 gradient; cost 0 chi^2, 1 likelihood; kind 0
+ * batched, 1 single-dataset; '#' starts a comment line.
+ * mu_autotune_save writes the file (MU_E_ARG if it cannot).  mu_autotune_load
+ * adds its choices to the context: MU_E_ARG, with nothing loaded, for a file
+ * that is missing, malformed or holds an out-of-range entry;
+ * MU_E_UNSUPPORTED, with nothing loaded, for a file written on another
+ * architecture.  mu_autotune_check_file validates a file without a device
+ * (same rules except the architecture) and writes a message into msg (may be
+ * NULL). */
+mu_status mu_autotune_save(mu_ctx *ctx, const char *path);
+mu_status mu_autotune_load(mu_ctx *ctx, const char *path);
+mu_status mu_autotune_check_file(const char *path, char *msg, int32_t msg_len);
+
 /* ----------------------------------------------------------------- fitting */
 
 /* Options of mu_fit_batch (zero-initialise, then set what you need). */
@@ -314,8 +353,13 @@ typedef struct {
   int32_t n_iter;  /* accepted variable-metric steps */
   int32_t n_fcn;   /* cost evaluations (gradient stencil points included) */
   int32_t n_grad;  /* gradient evaluations */
-  int32_t status;  /* 0 converged, 1 evaluation or iteration budget spent, 2 non-finite cost at the start,
-                      3 line search failed (params_out is the best point found) */
+  int32_t status;  /* 0 converged: the final EDM (after a polish, from the differenced Hessian) is below
+                      tol_edm, whatever stopped the iterations;
+                      1 evaluation or iteration budget spent with the final EDM above tol_edm;
+                      2 non-finite cost at the start;
+                      3 line search failed with the final EDM above tol_edm (params_out is the best point found);
+                      4 every step fell below tol_step_rel while the final EDM stayed above tol_edm (a nearly
+                        flat valley: the point is not a certified minimum) */
 } mu_fit_result;
 
 /* Minimise the cost of n_fits independent fits (Sec. 4: the fit of P by

@@ -105,6 +105,11 @@ def lib():
         "mu_autotune": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, C.c_int32, C.POINTER(C.c_int32),
                             C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "mu_autotune_set": (S, [vp, vp, vp, S, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "mu_autotune_batch": (S, [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), S, C.c_int32, vp, C.c_uint, C.c_int32,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "mu_autotune_save": (S, [vp, C.c_char_p]),
+        "mu_autotune_load": (S, [vp, C.c_char_p]),
+        "mu_autotune_check_file": (S, [C.c_char_p, C.c_char_p, C.c_int32]),
         "mu_histo_check": (S, [C.POINTER(mu_histo), C.c_int32, C.c_char_p, C.c_int32]),
         "mu_data_create": (S, [vp, C.POINTER(mu_histo), C.c_int32, C.POINTER(vp)]),
         "mu_data_destroy": (S, [vp]),
@@ -136,6 +141,7 @@ def exported_symbols():
     return sorted(["mu_abi_version", "mu_status_string", "mu_ctx_create", "mu_ctx_destroy", "mu_ctx_last_error",
                    "mu_ctx_synchronize", "mu_ctx_set_tile", "mu_ctx_get_tile", "mu_ctx_set_anchor", "mu_ctx_get_anchor",
                    "mu_ctx_set_specialize", "mu_ctx_timing", "mu_ctx_timing_read", "mu_autotune", "mu_autotune_set",
+                   "mu_autotune_batch", "mu_autotune_save", "mu_autotune_load", "mu_autotune_check_file",
                    "mu_histo_check", "mu_data_create",
                    "mu_data_destroy", "mu_data_bins", "mu_data_histos", "mu_data_is_f64", "mu_theory_check",
                    "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_chi2_eval", "mu_chi2_grad",

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import array
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -433,6 +434,51 @@ def autotune_set(ctx, data, theory, n_vec, tile, anchor, cost="chi2", grad=False
     dataset and theory, as if autotune had measured it."""
     _check(A.lib().mu_autotune_set(ctx.h, data.h, theory.h, _cost_code(cost), int(n_vec), 1 if grad else 0,
                                    int(tile), int(anchor)), ctx.h, "mu_autotune_set")
+
+
+def autotune_batch(ctx, datas, theories, params, cost="chi2", grad=False):
+    """Measure bins-per-wave / anchor candidates for batched launches of these
+    jobs and remember the fastest in the context.  params: [n_jobs, ld] host
+    array or CUDA tensor.  Returns (bins per wave, anchor, microseconds per call)."""
+    L = A.lib()
+    n = len(datas)
+    keep_d, dh = handle_array(datas)
+    keep_t, th = handle_array(theories)
+    bt, ba, us = C.c_int32(), C.c_int32(), C.c_double()
+    if _is_torch(params) and params.is_cuda:
+        import torch
+        p = params.detach().to(torch.float64).contiguous()
+        cur = ctx._enter_device()
+        _check(L.mu_autotune_batch(ctx.h, n, dh, th, _cost_code(cost), p.shape[1], C.c_void_p(p.data_ptr()),
+                                   A.MU_MEM_DEVICE, 1 if grad else 0, C.byref(bt), C.byref(ba), C.byref(us)),
+               ctx.h, "mu_autotune_batch")
+        ctx._leave_device(cur, [p])
+    else:
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        if p.ndim != 2 or p.shape[0] != n:
+            raise ValueError("params must have shape [n_jobs, ld]")
+        _check(L.mu_autotune_batch(ctx.h, n, dh, th, _cost_code(cost), p.shape[1], p.ctypes.data, A.MU_MEM_HOST,
+                                   1 if grad else 0, C.byref(bt), C.byref(ba), C.byref(us)), ctx.h,
+               "mu_autotune_batch")
+    return bt.value, ba.value, us.value
+
+
+def autotune_save(ctx, path):
+    """Write the context's remembered tuning choices to a text cache file."""
+    _check(A.lib().mu_autotune_save(ctx.h, os.fsencode(path)), ctx.h, "mu_autotune_save")
+
+
+def autotune_load(ctx, path):
+    """Add the choices of a tuning cache file to the context (raises on a
+    malformed file or one written for another architecture; nothing is loaded then)."""
+    _check(A.lib().mu_autotune_load(ctx.h, os.fsencode(path)), ctx.h, "mu_autotune_load")
+
+
+def autotune_check_file(path):
+    """Validate a tuning cache file without a device: (status, message)."""
+    msg = C.create_string_buffer(512)
+    st = A.lib().mu_autotune_check_file(os.fsencode(path), msg, len(msg))
+    return st, msg.value.decode()
 
 
 def fit_batch(ctx, datas, theories, start, cost="chi2", fixed=None, analytic_grad=True, batched=True,

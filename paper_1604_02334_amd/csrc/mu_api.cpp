@@ -357,45 +357,6 @@ extern "C" mu_status mu_histo_check(const mu_histo *h, int32_t n_histo, char *ms
   return s;
 }
 
-mu_status mu_data::tiles(int tile_bins, const TileSet **out) {
-  for (const TileSet &t : sets)
-    if (t.tile_bins == tile_bins) {
-      *out = &t;
-      return MU_OK;
-    }
-  std::vector<DevTile> tl;
-  std::vector<DevHisto> h2 = hh;
-  for (int j = 0; j < n_histo; ++j) {
-    h2[j].tile0 = (int32_t)tl.size();
-    for (int64_t b = 0; b < h2[j].n; b += tile_bins) {
-      DevTile t;
-      t.begin = b;
-      t.histo = j;
-      t.n = (int32_t)std::min<int64_t>(tile_bins, h2[j].n - b);
-      tl.push_back(t);
-    }
-  }
-  if (tl.size() > (size_t)INT32_MAX / 2) {
-    set_err(ctx, "dataset needs too many tiles");
-    return MU_E_UNSUPPORTED;
-  }
-  TileSet ts;
-  ts.tile_bins = tile_bins;
-  ts.n_tiles = (int32_t)tl.size();
-  hipError_t e = hipMalloc(&ts.d_tiles, tl.size() * sizeof(DevTile));
-  if (e == hipSuccess) e = hipMalloc(&ts.d_histos, h2.size() * sizeof(DevHisto));
-  if (e == hipSuccess) e = hipMemcpy(ts.d_tiles, tl.data(), tl.size() * sizeof(DevTile), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ts.d_histos, h2.data(), h2.size() * sizeof(DevHisto), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    if (ts.d_tiles) hipFree(ts.d_tiles);
-    if (ts.d_histos) hipFree(ts.d_histos);
-    return hip_fail(ctx, e, "tile tables");
-  }
-  sets.push_back(ts);
-  *out = &sets.back();
-  return MU_OK;
-}
-
 // The gradient merge plan of (th, this dataset); layout next to kPlanHead.
 mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out) {
   for (const Plan &p : plans)
@@ -472,18 +433,11 @@ void mu_data::free_dev() {
   counts = nullptr;
   if (d_hh) hipFree(d_hh);
   d_hh = nullptr;
-  for (TileSet &t : sets) {
-    if (t.d_tiles) hipFree(t.d_tiles);
-    if (t.d_histos) hipFree(t.d_histos);
-  }
-  sets.clear();
 }
 
-// Tile size for a launch: the tuned choice for this (shape, mode, cost, size)
-// if one was measured, else about 64 tiles per compute unit with tiles of
-// 1024 .. 65536 bins.
-// Key of the tuned table: theory shape, mode, cost, launch kind (tile or
-// split) and the size of the launch to a power of two.
+// Key of the tuned table: theory shape (kShapeCount: a batched launch of
+// compiled shapes), mode, cost, launch kind (batched or single-dataset) and
+// the size of the launch to a power of two.
 static int tune_key(int shape, int mode, int cost, int split, int64_t work) {
   int lg = 0;
   while (((int64_t)1 << (lg + 1)) <= work) ++lg;
@@ -507,26 +461,19 @@ int64_t mu_ctx::pick_split(int shape, int mode, int cost, int count_f64, int64_t
   return std::max<int64_t>(kWave, (work + cap - 1) / cap);
 }
 
-int mu_ctx::pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const {
+int64_t mu_ctx::pick_batch(int generic, int mode, int cost, int count_f64, int64_t work, int *anchor) const {
   *anchor = anchor_every;
   if (tile_bins > 0) return tile_bins;
-  const int key = tune_key(shape, mode, cost, 0, work);
+  const int key = tune_key(generic ? kShapeGeneric : kShapeCount, mode, cost, 0, work);
   for (const Tuned &t : tuned)
     if (t.key == key) {
       *anchor = t.anchor;
       return t.tile;
     }
-  // about 64 tiles (waves) per compute unit over the whole batch: a batch is
-  // one launch per theory shape, so each launch gets a share of that, and a
-  // few rounds of resident waves balance uneven histograms (on 512 datasets
-  // of 2^12 .. 2^20 bins in four shapes: 143 us at 4096-8192 bins per tile,
-  // 187 us at 16384)
-  int64_t want = work / (64 * std::max(n_cu, 1));
-  int tile = kMinTile;
-  while (tile < kMaxTile && (int64_t)tile * 2 <= want) tile *= 2;
-  // no tile longer than the longest histogram needs
-  while (tile > kMinTile && (int64_t)tile / 2 >= longest) tile /= 2;
-  return tile;
+  // one range per resident wave of the launch's kernel, at least one bin per lane
+  const int per_cu = eval_batch_blocks_per_cu(mode, cost, count_f64, generic);
+  const int64_t cap = (int64_t)std::max(per_cu, 1) * (kBlock / kWave) * std::max(n_cu, 1);
+  return std::max<int64_t>(kWave, (work + cap - 1) / cap);
 }
 
 extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_histo, mu_data **out) {
@@ -554,7 +501,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
     x.t0_bin = h[j].t0_bin;
     x.dt = h[j].dt;
     x.map_row = h[j].map_row;
-    x.tile0 = 0;
+    x.pad = 0;
     d->max_row = std::max(d->max_row, (int)h[j].map_row);
     d->longest = std::max(d->longest, x.n);
     total += x.n;
@@ -929,6 +876,7 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   const int64_t work = (int64_t)n_vec * d->total;
   int64_t W = ctx->pick_split(shape, mode, cost_kind, d->f64, work, &anchor);
   if (w_force > 0) W = w_force;
+  if (mode == kModeGrad) W = std::min<int64_t>(W, kMaxGradSplit);
   const int n_par = th->h.n_par;
   const int64_t n_units = (work + W - 1) / W;
   if (n_units + (int64_t)n_vec * d->n_histo > INT32_MAX) {
@@ -948,19 +896,19 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   a.tmpl.plan = plan;
   a.tmpl.histos = d->d_hh;
   a.tmpl.counts = d->counts;
-  a.tmpl.tiles = nullptr;
   a.tmpl.p = dp;
   a.tmpl.cost_out = dc;
   a.tmpl.histo_out = dh;
   a.tmpl.grad_out = dg;
   a.tmpl.model_out = dm;
-  a.tmpl.n_tiles = 0;
   a.tmpl.n_histo = d->n_histo;
+  a.tmpl.shape = shape;
   a.p_stride = n_par;
   a.grad_stride = n_par;
   a.histo_stride = d->n_histo;
   a.jobs = nullptr;
-  a.unit_job = nullptr;
+  a.job_list = nullptr;
+  a.unit_start = nullptr;
   a.n_units = (int32_t)n_units;
   a.cost_kind = cost_kind;
   a.anchor_every = anchor;
@@ -1228,52 +1176,82 @@ extern "C" mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *c
     }
   }
   hipSetDevice(ctx->device);
-  int64_t work = 0, longest = 0;
-  for (int j = 0; j < n_jobs; ++j) {
-    work += data[j]->total;
-    longest = std::max(longest, data[j]->longest);
-  }
-  int anchor = ctx->anchor_every;
-  const int tile = ctx->pick_tile(kShapeGeneric, grad ? kModeGrad : kModeCost, cost_kind, work, longest, &anchor);
-  std::vector<const TileSet *> sets(n_jobs);
-  int64_t n_units = 0;
-  for (int j = 0; j < n_jobs; ++j) {
-    if ((st = const_cast<mu_data *>(data[j])->tiles(tile, &sets[j])) != MU_OK) return st;
-    n_units += sets[j]->n_tiles;
-  }
-  if (n_units > INT32_MAX) {
-    set_err(ctx, "launch needs more than 2^31 work units");
-    return MU_E_UNSUPPORTED;
-  }
-  return run_batch(ctx, n_jobs, data, sets.data(), th, cost_kind, ld, params, mem, cost, grad, n_units, anchor);
+  return run_batch(ctx, n_jobs, data, th, cost_kind, ld, params, mem, cost, grad);
 }
 
 namespace mu {
 
-mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
-                    const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
-                    double *cost, double *grad, int64_t n_units, int anchor) {
+mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,
+                    int cost_kind, int32_t ld, const double *params, unsigned mem, double *cost, double *grad) {
   mu_status st;
   hipError_t e;
+  const int mode = grad ? kModeGrad : kModeCost;
+  const int f64 = data[0]->f64;
+  // launch 0: jobs of compiled shapes (each segment runs its job's shape);
+  // launch 1: the others (interpreted theory programs, or FP64 counts)
+  std::vector<int32_t> list;
+  list.reserve(n_jobs);
+  struct Group {
+    int32_t first = 0, n = 0;  // in `list`
+    int64_t total = 0, W = 0, n_units = 0;
+    int32_t n_histo = 0, slot_base = 0, anchor = 0, in_table = 1;
+  } grp[2];
+  for (int g = 0; g < 2; ++g) {
+    Group &G = grp[g];
+    G.first = (int32_t)list.size();
+    for (int j = 0; j < n_jobs; ++j) {
+      const bool fixed = ctx->specialize && !f64 && th[j]->shape != kShapeGeneric;
+      if (fixed != (g == 0)) continue;
+      list.push_back(j);
+      G.total += data[j]->total;
+      G.n_histo += data[j]->n_histo;
+      if (data[j]->f64 || data[j]->max_count >= kInvTab) G.in_table = 0;
+    }
+    G.n = (int32_t)list.size() - G.first;
+  }
+  int64_t slots = 0, units_all = 0;
+  for (int g = 0; g < 2; ++g) {
+    Group &G = grp[g];
+    if (G.n == 0) continue;
+    int anchor = ctx->anchor_every;
+    G.W = ctx->pick_batch(g == 1, mode, cost_kind, f64, G.total, &anchor);
+    if (mode == kModeGrad) G.W = std::min<int64_t>(G.W, kMaxGradSplit);
+    G.anchor = anchor;
+    G.n_units = (G.total + G.W - 1) / G.W;
+    G.slot_base = (int32_t)std::min<int64_t>(slots, INT32_MAX);
+    slots += G.n_units + G.n_histo;
+    units_all += G.n_units;
+  }
+  if (slots > INT32_MAX) {
+    set_err(ctx, "launch needs more than 2^31 work units");
+    return MU_E_UNSUPPORTED;
+  }
   const size_t n_p = (size_t)n_jobs * ld;
   const size_t n_c = (size_t)n_jobs;
   const size_t n_g = grad ? (size_t)n_jobs * ld : 0;
   const size_t jobs_bytes = (size_t)n_jobs * sizeof(DevJob);
-  const size_t map_bytes = (size_t)n_units * sizeof(int32_t);
-  const size_t meta = ((jobs_bytes + map_bytes + 255) & ~size_t(255));
+  const size_t list_bytes = (size_t)n_jobs * sizeof(int32_t);
+  const size_t start_bytes = (size_t)units_all * 2 * sizeof(int32_t);
+  const size_t meta = ((jobs_bytes + list_bytes + start_bytes + 255) & ~size_t(255));
   const size_t up_bytes = meta + (mem == MU_MEM_HOST ? n_p * sizeof(double) : 0);
   if ((st = ctx->djobs.ensure(ctx, up_bytes, false)) != MU_OK) return st;
   if ((st = ctx->staging.ensure(ctx, up_bytes)) != MU_OK) return st;
-  if ((st = ctx->partial.ensure(ctx, (size_t)n_units * kSlot * sizeof(double), false)) != MU_OK) return st;
+  if ((st = ctx->partial.ensure(ctx, (size_t)slots * kSlot * sizeof(double), false)) != MU_OK) return st;
   if (mem == MU_MEM_HOST) {
     if ((st = ctx->dout.ensure(ctx, (n_c + n_g) * sizeof(double), false)) != MU_OK) return st;
     if ((st = ctx->staging_out.ensure(ctx, (n_c + n_g) * sizeof(double))) != MU_OK) return st;
   }
+  // gradient merge plans first (they may upload)
+  std::vector<const int32_t *> plans(n_jobs, nullptr);
+  if (grad)
+    for (int j = 0; j < n_jobs; ++j)
+      if ((st = const_cast<mu_data *>(data[j])->grad_plan(th[j], &plans[j])) != MU_OK) return st;
   ctx->wait_staging();
   char *up = static_cast<char *>(ctx->staging.ptr);
   char *dup = static_cast<char *>(ctx->djobs.ptr);
   DevJob *jobs = reinterpret_cast<DevJob *>(up);
-  int32_t *bj = reinterpret_cast<int32_t *>(up + jobs_bytes);
+  int32_t *hl = reinterpret_cast<int32_t *>(up + jobs_bytes);
+  int32_t *hs = reinterpret_cast<int32_t *>(up + jobs_bytes + list_bytes);
   const double *dp = params;
   if (mem == MU_MEM_HOST) {
     std::memcpy(up + meta, params, n_p * sizeof(double));
@@ -1284,62 +1262,79 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     dc = static_cast<double *>(ctx->dout.ptr);
     dg = grad ? dc + n_c : nullptr;
   }
-  // jobs keep their order (and partial slots); units are grouped by theory
-  // shape so each group runs its compiled specialisation
-  int32_t slot_base = 0;
-  for (int j = 0; j < n_jobs; ++j) {
-    DevJob &J = jobs[j];
-    std::memset(&J, 0, sizeof J);
-    J.th = th[j]->d_th;
-    J.histos = sets[j]->d_histos;
-    J.counts = data[j]->counts;
-    J.tiles = sets[j]->d_tiles;
-    J.p = dp + (size_t)j * ld;
-    J.cost_out = dc + j;
-    J.histo_out = nullptr;
-    J.grad_out = dg ? dg + (size_t)j * ld : nullptr;
-    J.model_out = nullptr;
-    J.plan = nullptr;
-    if (grad && (st = const_cast<mu_data *>(data[j])->grad_plan(th[j], &J.plan)) != MU_OK) return st;
-    J.n_tiles = sets[j]->n_tiles;
-    J.n_histo = data[j]->n_histo;
-    J.tile_base = slot_base;
-    slot_base += J.n_tiles;
-  }
-  int group_first[kShapeCount + 1];
-  int32_t filled = 0;
-  for (int shp = 0; shp < kShapeCount; ++shp) {
-    group_first[shp] = filled;
-    for (int j = 0; j < n_jobs; ++j) {
-      const int js = ctx->specialize ? th[j]->shape : kShapeGeneric;
-      if (js != shp) continue;
-      jobs[j].unit_base = filled - group_first[shp];
-      for (int k = 0; k < jobs[j].n_tiles; ++k) bj[filled + k] = j;
-      filled += jobs[j].n_tiles;
+  std::memcpy(hl, list.data(), list_bytes);
+  int64_t start_at = 0;  // first unit_start entry of the group
+  int64_t start_of[2] = {0, 0};
+  for (int g = 0; g < 2; ++g) {
+    const Group &G = grp[g];
+    start_of[g] = start_at;
+    if (G.n == 0) continue;
+    int64_t goff = 0;
+    int32_t jbase = 0;
+    for (int li = G.first; li < G.first + G.n; ++li) {
+      const int j = list[li];
+      DevJob &J = jobs[j];
+      std::memset(&J, 0, sizeof J);
+      J.th = th[j]->d_th;
+      J.histos = data[j]->d_hh;
+      J.counts = data[j]->counts;
+      J.p = dp + (size_t)j * ld;
+      J.cost_out = dc + j;
+      J.grad_out = dg ? dg + (size_t)j * ld : nullptr;
+      J.plan = plans[j];
+      J.goff = goff;
+      J.split_w = G.W;
+      J.jbase = jbase;
+      J.slot_base = G.slot_base;
+      J.n_histo = data[j]->n_histo;
+      J.shape = g == 0 ? th[j]->shape : kShapeGeneric;
+      goff += data[j]->total;
+      jbase += data[j]->n_histo;
     }
+    // where each unit's range starts: (job-list entry within the group, histogram)
+    int li = 0, h = 0;
+    int64_t hend = data[list[G.first]]->hh[0].n;
+    int64_t jstart = 0;
+    for (int64_t u = 0; u < G.n_units; ++u) {
+      const int64_t pos = u * G.W;
+      while (pos >= hend) {
+        const mu_data *dj = data[list[G.first + li]];
+        if (++h == dj->n_histo) {
+          h = 0;
+          jstart += dj->total;
+          ++li;
+        }
+        const mu_data *dn = data[list[G.first + li]];
+        hend = jstart + dn->hh[h].off + dn->hh[h].n;
+      }
+      hs[2 * (start_at + u)] = li;
+      hs[2 * (start_at + u) + 1] = h;
+    }
+    start_at += G.n_units;
   }
-  group_first[kShapeCount] = filled;
   e = hipMemcpyAsync(dup, up, up_bytes, hipMemcpyHostToDevice, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(jobs)");
   ctx->mark_staging();
-  for (int shp = 0; shp < kShapeCount; ++shp) {
-    const int nb = group_first[shp + 1] - group_first[shp];
-    if (nb == 0) continue;
+  double *part = static_cast<double *>(ctx->partial.ptr);
+  for (int g = 0; g < 2; ++g) {
+    const Group &G = grp[g];
+    if (G.n == 0) continue;
     LaunchArgs a;
     std::memset(&a, 0, sizeof a);
     a.jobs = reinterpret_cast<const DevJob *>(dup);
-    a.unit_job = reinterpret_cast<const int32_t *>(dup + jobs_bytes) + group_first[shp];
-    a.n_units = nb;
+    a.job_list = reinterpret_cast<const int32_t *>(dup + jobs_bytes) + G.first;
+    a.unit_start = reinterpret_cast<const int32_t *>(dup + jobs_bytes + list_bytes) + 2 * start_of[g];
+    a.n_units = (int32_t)G.n_units;
+    a.n_vec = G.n;
+    a.split_w = G.W;
+    a.total = G.total;
     a.cost_kind = cost_kind;
-    a.anchor_every = ctx->anchor_every;
+    a.anchor_every = G.anchor;
     a.inv_src = ctx->d_inv;
-    a.counts_in_table = 1;
-    for (int j = 0; j < n_jobs; ++j)
-      if ((ctx->specialize ? th[j]->shape : kShapeGeneric) == shp && (data[j]->f64 || data[j]->max_count >= kInvTab))
-        a.counts_in_table = 0;
-    a.partial = static_cast<double *>(ctx->partial.ptr);
+    a.counts_in_table = G.in_table;
+    a.partial = part + (size_t)G.slot_base * kSlot;
     const int ti = ctx->time_begin(grad ? MU_TIME_EVAL_GRAD : MU_TIME_EVAL_COST, ctx->stream);
-    e = launch_eval(a, grad ? kModeGrad : kModeCost, data[0]->f64, shp, ctx->stream);
+    e = launch_eval_batch(a, mode, f64, g == 1, ctx->stream);
     ctx->time_end(ti, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched evaluation launch");
   }
@@ -1347,9 +1342,9 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     LaunchArgs m;
     std::memset(&m, 0, sizeof m);
     m.jobs = reinterpret_cast<const DevJob *>(dup);
-    m.partial = static_cast<double *>(ctx->partial.ptr);
+    m.partial = part;
     const int ti = ctx->time_begin(MU_TIME_MERGE, ctx->stream);
-    e = launch_merge(m, grad ? kModeGrad : kModeCost, n_jobs, ctx->stream);
+    e = launch_merge(m, mode, n_jobs, ctx->stream);
     ctx->time_end(ti, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
   }
@@ -1375,10 +1370,7 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
 
 // The tuned (tile, anchor) of single-dataset launches of this theory's shape,
 // mode, cost and size.
-static void remember_tuned(mu_ctx *ctx, const mu_theory *th, int mode, int cost_kind, int64_t work, int tile,
-                           int anchor) {
-  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
-  const int key = tune_key(shape, mode, cost_kind, 1, work);
+static void remember_key(mu_ctx *ctx, int key, int tile, int anchor) {
   for (auto &t : ctx->tuned)
     if (t.key == key) {
       t.tile = tile;
@@ -1386,6 +1378,14 @@ static void remember_tuned(mu_ctx *ctx, const mu_theory *th, int mode, int cost_
       return;
     }
   ctx->tuned.push_back({key, tile, anchor});
+}
+
+// The tuned (tile, anchor) of single-dataset launches of this theory's shape,
+// mode, cost and size.
+static void remember_tuned(mu_ctx *ctx, const mu_theory *th, int mode, int cost_kind, int64_t work, int tile,
+                           int anchor) {
+  const int shape = ctx->specialize ? th->shape : kShapeGeneric;
+  remember_key(ctx, tune_key(shape, mode, cost_kind, 1, work), tile, anchor);
 }
 
 extern "C" mu_status mu_autotune_set(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
@@ -1502,5 +1502,251 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   if (best_tile) *best_tile = (int32_t)bt;
   if (best_anchor) *best_anchor = ba;
   if (best_us) *best_us = best / 5.0 * 1e3;
+  return MU_OK;
+}
+
+// Batched launches: the (bins per wave, anchor) pair that runs a batch of
+// jobs fastest, remembered for batched launches of the same kind, mode, cost
+// and size (to a power of two).
+extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data,
+                                       const mu_theory *const *th, mu_cost cost_kind, int32_t ld,
+                                       const double *params, unsigned mem, int32_t grad, int32_t *best_tile,
+                                       int32_t *best_anchor, double *best_us) {
+  if (!ctx) return MU_E_ARG;
+  if (n_jobs < 1 || !data || !th || !params || ld < 1 || (mem != MU_MEM_HOST && mem != MU_MEM_DEVICE) ||
+      (cost_kind != MU_COST_CHI2 && cost_kind != MU_COST_POISSON)) {
+    set_err(ctx, "autotune_batch needs n_jobs >= 1, data, theories, parameters, ld >= 1, a memory kind and a cost kind");
+    return MU_E_ARG;
+  }
+  mu_status st;
+  for (int j = 0; j < n_jobs; ++j) {
+    if ((st = check_pair(ctx, data[j], th[j])) != MU_OK) return st;
+    if (th[j]->h.n_par > ld || data[j]->f64 != data[0]->f64) {
+      set_err(ctx, "job %d: more parameters than ld, or mixed count storage", j);
+      return MU_E_ARG;
+    }
+  }
+  hipSetDevice(ctx->device);
+  const int mode = grad ? kModeGrad : kModeCost;
+  const int f64 = data[0]->f64;
+  // the two launch groups of run_batch and their sizes
+  int64_t total[2] = {0, 0};
+  for (int j = 0; j < n_jobs; ++j) {
+    const bool fixed = ctx->specialize && !f64 && th[j]->shape != kShapeGeneric;
+    total[fixed ? 0 : 1] += data[j]->total;
+  }
+  const int lead = total[0] > 0 ? 0 : 1;
+  const size_t n_p = (size_t)n_jobs * ld;
+  double *buf = nullptr;
+  hipError_t e = hipMalloc(&buf, (n_p + (size_t)n_jobs + (grad ? n_p : 0)) * sizeof(double));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(autotune)");
+  e = hipMemcpyAsync(buf, params, n_p * sizeof(double),
+                     mem == MU_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream);
+  double *dc = buf + n_p, *dg = grad ? dc + n_jobs : nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const int saved_tile = ctx->tile_bins, saved_anchor = ctx->anchor_every;
+  std::vector<double> ref(n_jobs), cur(n_jobs);
+  bool have_ref = false;
+  int64_t bt = 0;
+  int ba = 0;
+  float best = 1e30f;
+  std::vector<int64_t> cand;
+  {
+    const int per_cu = eval_batch_blocks_per_cu(mode, cost_kind, f64, lead);
+    const int64_t cap = (int64_t)std::max(per_cu, 1) * (kBlock / kWave) * std::max(ctx->n_cu, 1);
+    for (int m : {1, 2, 3, 4, 6, 8}) {
+      const int64_t w = std::max<int64_t>(kWave, (total[lead] + m * cap - 1) / (m * cap));
+      if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
+    }
+    for (int64_t w = kMinTile; w <= kMaxTile && w < total[lead]; w *= 2)
+      if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
+  }
+  st = e == hipSuccess ? MU_OK : hip_fail(ctx, e, "hipMemcpyAsync(autotune)");
+  for (size_t ci = 0; ci < cand.size() && st == MU_OK; ++ci) {
+    for (int anchor : {32, 64, 128, 256}) {
+      ctx->tile_bins = (int)std::min<int64_t>(cand[ci], kMaxSplit);
+      ctx->anchor_every = anchor;
+      for (int w = 0; w < 2 && st == MU_OK; ++w)
+        st = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
+      if (st != MU_OK) break;
+      hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < 5 && st == MU_OK; ++r)
+        st = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
+      hipEventRecord(e1, ctx->stream);
+      if (st != MU_OK) break;
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      // every candidate must reproduce the first one's costs to rounding
+      hipMemcpy(cur.data(), dc, n_jobs * sizeof(double), hipMemcpyDeviceToHost);
+      bool ok = true;
+      if (!have_ref) {
+        ref = cur;
+        have_ref = true;
+      } else {
+        for (int j = 0; j < n_jobs; ++j)
+          if (!(std::fabs(cur[j] - ref[j]) <= 1e-12 * std::fabs(ref[j])) && !(std::isnan(cur[j]) && std::isnan(ref[j])))
+            ok = false;
+      }
+      if (ok && ms < best) {
+        best = ms;
+        bt = ctx->tile_bins;
+        ba = anchor;
+      }
+    }
+  }
+  ctx->tile_bins = saved_tile;
+  ctx->anchor_every = saved_anchor;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamSynchronize(ctx->stream);
+  hipFree(buf);
+  if (st != MU_OK) return st;
+  if (bt == 0) {
+    set_err(ctx, "no tuning candidate ran");
+    return MU_E_DEVICE;
+  }
+  for (int g = 0; g < 2; ++g)
+    if (total[g] > 0) remember_key(ctx, tune_key(g == 1 ? kShapeGeneric : kShapeCount, mode, cost_kind, 0, total[g]),
+                                   (int)bt, ba);
+  if (best_tile) *best_tile = (int32_t)bt;
+  if (best_anchor) *best_anchor = ba;
+  if (best_us) *best_us = best / 5.0 * 1e3;
+  return MU_OK;
+}
+
+// ------------------------------------------------------- tuning cache file
+//
+//   mu-autotune 1
+//   arch <device architecture name>
+//   <shape> <mode> <cost> <kind> <log2 size> <bins per wave> <anchor>   (one line per choice)
+//
+// shape: 0 interpreted, 1..5 compiled shapes, 6 batched launch of compiled
+// shapes; mode: 0 cost, 1 gradient; cost: 0 chi^2, 1 likelihood; kind:
+// 0 batched, 1 single-dataset launch.
+
+namespace {
+
+struct CacheEntry {
+  int shape, mode, cost, kind, lg, tile, anchor;
+};
+
+mu_status parse_cache(const char *path, std::string &arch, std::vector<CacheEntry> &out, std::string &why) {
+  FILE *f = path ? std::fopen(path, "r") : nullptr;
+  if (!f) {
+    why = std::string("cannot open tuning cache ") + (path ? path : "(null)");
+    return MU_E_ARG;
+  }
+  char line[512];
+  int ln = 0;
+  mu_status st = MU_OK;
+  bool head = false, have_arch = false;
+  while (std::fgets(line, sizeof line, f)) {
+    ++ln;
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r' || l.back() == ' ')) l.pop_back();
+    if (l.empty() || l[0] == '#') continue;
+    if (!head) {
+      if (l != "mu-autotune 1") {
+        why = "tuning cache: line " + std::to_string(ln) + ": expected the header 'mu-autotune 1'";
+        st = MU_E_ARG;
+        break;
+      }
+      head = true;
+      continue;
+    }
+    if (!have_arch) {
+      char a[128];
+      if (std::sscanf(l.c_str(), "arch %127s", a) != 1) {
+        why = "tuning cache: line " + std::to_string(ln) + ": expected 'arch <name>'";
+        st = MU_E_ARG;
+        break;
+      }
+      arch = a;
+      have_arch = true;
+      continue;
+    }
+    CacheEntry c;
+    char extra;
+    if (std::sscanf(l.c_str(), "%d %d %d %d %d %d %d %c", &c.shape, &c.mode, &c.cost, &c.kind, &c.lg, &c.tile,
+                    &c.anchor, &extra) != 7 ||
+        c.shape < 0 || c.shape > kShapeCount || c.mode < 0 || c.mode > 1 || c.cost < 0 || c.cost > 1 || c.kind < 0 ||
+        c.kind > 1 || c.lg < 0 || c.lg > 62 || c.tile < kWave || c.tile > kMaxSplit || c.anchor < 1 ||
+        c.anchor > 256) {
+      why = "tuning cache: line " + std::to_string(ln) + ": malformed or out-of-range entry";
+      st = MU_E_ARG;
+      break;
+    }
+    out.push_back(c);
+  }
+  std::fclose(f);
+  if (st == MU_OK && (!head || !have_arch)) {
+    why = "tuning cache: missing header or architecture line";
+    st = MU_E_ARG;
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" mu_status mu_autotune_check_file(const char *path, char *msg, int32_t msg_len) {
+  std::string arch, why;
+  std::vector<CacheEntry> e;
+  const mu_status st = parse_cache(path, arch, e, why);
+  put_msg(msg, msg_len, st == MU_OK ? "ok: " + std::to_string(e.size()) + " entries for " + arch : why);
+  return st;
+}
+
+extern "C" mu_status mu_autotune_save(mu_ctx *ctx, const char *path) {
+  if (!ctx || !path) return MU_E_ARG;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDeviceProperties");
+  FILE *f = std::fopen(path, "w");
+  if (!f) {
+    set_err(ctx, "cannot write tuning cache %s", path);
+    return MU_E_ARG;
+  }
+  std::fprintf(f, "mu-autotune 1\narch %s\n# shape mode cost kind log2_size bins_per_wave anchor\n", prop.gcnArchName);
+  for (const auto &t : ctx->tuned) {
+    int k = t.key;
+    const int lg = k % 64;
+    k /= 64;
+    const int kind = k % 2;
+    k /= 2;
+    const int cost = k % 2;
+    k /= 2;
+    const int mode = k % 4;
+    const int shape = k / 4;
+    std::fprintf(f, "%d %d %d %d %d %d %d\n", shape, mode, cost, kind, lg, t.tile, t.anchor);
+  }
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) {
+    set_err(ctx, "writing tuning cache %s failed", path);
+    return MU_E_ARG;
+  }
+  return MU_OK;
+}
+
+extern "C" mu_status mu_autotune_load(mu_ctx *ctx, const char *path) {
+  if (!ctx) return MU_E_ARG;
+  std::string arch, why;
+  std::vector<CacheEntry> ent;
+  mu_status st = parse_cache(path, arch, ent, why);
+  if (st != MU_OK) {
+    set_err(ctx, "%s", why.c_str());
+    return st;
+  }
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDeviceProperties");
+  if (arch != prop.gcnArchName) {
+    set_err(ctx, "tuning cache was written for %s, this device is %s", arch.c_str(), prop.gcnArchName);
+    return MU_E_UNSUPPORTED;
+  }
+  for (const CacheEntry &c : ent)
+    remember_key(ctx, (((c.shape * 4 + c.mode) * 2 + c.cost) * 2 + c.kind) * 64 + c.lg, c.tile, c.anchor);
   return MU_OK;
 }

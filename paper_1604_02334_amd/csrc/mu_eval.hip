@@ -27,8 +27,9 @@
 // anchors keep every factor within ~4e-12 relative of its directly evaluated
 // value.  ge (beta free) is evaluated directly.
 //
-// Reduction: per lane a plain FP64 sum over its bins, then compensated
-// (TwoSum) merges across the wave and across the segments of the job.  Each
+// Reduction: per lane a plain FP64 sum over one anchor interval (at most 256
+// bins), folded into a compensated (TwoSum) pair at every anchor, then
+// compensated merges across the wave and across the segments of the job.  Each
 // segment writes its own slot; a second, one-workgroup-per-job kernel merges
 // the job's slots in a fixed order, so results are bitwise reproducible and
 // no atomics or device-scope fences are used.
@@ -74,6 +75,7 @@ struct TStruct {
 
 struct ShapeGeneric {
   static constexpr bool kFixed = false;
+  static constexpr int kTerms = 0;
   static constexpr bool kScalable = false;
   __device__ static int nt(const TStruct &ts) { return ts.nt; }
   __device__ static int nf(const TStruct &ts, int k) { return ts.nf[k]; }
@@ -84,6 +86,7 @@ struct ShapeGeneric {
 template <int NT, int NF0, int P00, int P01, int NF1, int P10, int P11>
 struct ShapeFixed {
   static constexpr bool kFixed = true;
+  static constexpr int kTerms = NT;
   // Cost and model passes may fold N0, the lifetime and each term's weight
   // into the state of the term's first factor when that factor follows a
   // linear recurrence (se, sg, tf) or is a lone stg (its constant part then
@@ -223,7 +226,6 @@ __device__ __forceinline__ DevHisto uni(DevHisto x) {
   x.t0_bin = uni(x.t0_bin);
   x.dt = uni(x.dt);
   x.map_row = uni(x.map_row);
-  x.tile0 = uni(x.tile0);
   return x;
 }
 
@@ -464,22 +466,6 @@ __device__ __forceinline__ double cost_add(double acc, double x, double N, doubl
   return acc + cost_term<COST, false, INT_DATA>(INT_DATA ? x * kCountUnscale : x, N, iv_int, dN);
 }
 
-__device__ __forceinline__ DevJob job_of(const LaunchArgs &a, int b, int &job) {
-  if (a.jobs == nullptr) {
-    job = b / a.tmpl.n_tiles;
-    DevJob J = a.tmpl;
-    J.p += job * a.p_stride;
-    J.cost_out += job;
-    if (J.histo_out) J.histo_out += job * a.histo_stride;
-    if (J.grad_out) J.grad_out += job * a.grad_stride;
-    J.tile_base = job * a.tmpl.n_tiles;
-    J.unit_base = J.tile_base;
-    return J;
-  }
-  job = a.unit_job[b];
-  return a.jobs[job];
-}
-
 // ------------------------------------------------------------ merge kernel
 
 // Compensated sum of slot component `c` over tiles k0, k0 + step, ... < k1:
@@ -530,34 +516,24 @@ __device__ double sum_slot_pairs(const double *P, int k0, int k1) {
   return pair_value(t);
 }
 
-// Merge the tile slots of job J in a fixed order and write its outputs.
-// Slots of one job: per histogram a contiguous range, and the span of all of
-// them (tile launch: the job's tile table; split launch: unit + histogram
-// index of each segment).
+// Merge the slots of job J in a fixed order and write its outputs. Segment
+// (unit u, histogram j of the launch's enumeration) owns slot u + j, so the
+// slots of one histogram are a contiguous range, and the span of a job's
+// histograms holds no undefined slot.
 struct SlotMap {
   const double *P;
   const DevJob *J;
-  int64_t W, vbase;  // split launch: bins per unit, first bin of the vector
-  int jbase;         // split launch: v * n_histo
+  int64_t W, vbase;  // bins per unit, first bin of the job in its launch
+  int jbase;         // the job's first histogram in its launch's enumeration
   __device__ void range(int h, int &k0, int &k1) const {
-    if (W == 0) {
-      k0 = J->histos[h].tile0;
-      k1 = (h + 1 < J->n_histo) ? J->histos[h + 1].tile0 : J->n_tiles;
-    } else {
-      const int64_t s = vbase + J->histos[h].off;
-      k0 = (int)(jbase + h + s / W);
-      k1 = (int)(jbase + h + (s + J->histos[h].n - 1) / W) + 1;
-    }
+    const int64_t s = vbase + J->histos[h].off;
+    k0 = (int)(jbase + h + s / W);
+    k1 = (int)(jbase + h + (s + J->histos[h].n - 1) / W) + 1;
   }
   __device__ void span(int &k0, int &k1) const {
-    if (W == 0) {
-      k0 = 0;
-      k1 = J->n_tiles;
-    } else {
-      int t;
-      range(0, k0, t);
-      range(J->n_histo - 1, t, k1);
-    }
+    int t;
+    range(0, k0, t);
+    range(J->n_histo - 1, t, k1);
   }
 };
 
@@ -576,10 +552,17 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   SlotMap sm;
   sm.J = &J;
-  sm.W = (a.jobs == nullptr) ? a.split_w : 0;
-  sm.P = sm.W ? a.partial : a.partial + (int64_t)J.tile_base * kSlot;
-  sm.vbase = (int64_t)job * a.total;
-  sm.jbase = job * J.n_histo;
+  if (a.jobs == nullptr) {
+    sm.W = a.split_w;
+    sm.P = a.partial;
+    sm.vbase = (int64_t)job * a.total;
+    sm.jbase = job * J.n_histo;
+  } else {
+    sm.W = J.split_w;
+    sm.P = a.partial + (int64_t)J.slot_base * kSlot;
+    sm.vbase = J.goff;
+    sm.jbase = J.jbase;
+  }
   const double *P = sm.P;
   const DevTheory *th = J.th;
   const int n_par = G ? th->n_par : 0;
@@ -752,6 +735,11 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   // where they stayed live across it in spilled scalar registers.
   int lane = tid & 63;
   asm volatile("" : "+v"(lane));
+  // one LDS word per lane: the wave's function values in the prologue, then
+  // the lane's compensation term
+  static_assert(kFunStage <= kWave, "function stage within the wave's words");
+  __shared__ double f_stage[kBlock / kWave][kWave];
+  double *f_lane = &f_stage[tid / kWave][tid & (kWave - 1)];
   // resolved scalars of this (vector, histogram): lane r of every wave
   // resolves scalar r, then each is broadcast to scalar registers
   double R[kRS];
@@ -760,8 +748,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     // wave forms each dot product lane-parallel with a fixed-order sum and
     // shares them through its LDS row (a serial loop per scalar would wait on
     // n_par loads)
-    __shared__ double f_all[kBlock / kWave][kFunStage];
-    double *f_s = f_all[tid / kWave];  // this wave's copy
+    double *f_s = f_stage[tid / kWave];  // this wave's copy
     const int n_fun = __builtin_amdgcn_readfirstlane(th->n_fun);
     const bool f_staged = n_fun > 0 && n_fun <= kFunStage;
     if (f_staged) {
@@ -907,7 +894,24 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) s0[s] = s1[s] = u[s] = 0.0;
 
-  double lane_cost = 0.0;
+  // Cost pass: the lane's cost runs as a plain sum over one anchor interval
+  // (at most 256 terms); at every anchor that sum is folded into the lane's
+  // total by TwoSum, whose exact error accumulates in the lane's LDS word
+  // (the stage of the function values, unused after the prologue), so the
+  // lane's rounding error stays bounded however many bins the segment gives
+  // it. The gradient pass sums plainly per lane (its ranges are capped at
+  // kMaxGradSplit bins per wave, so at most 2^14 terms per lane).
+  double lane_cost = 0.0, lane_sum = 0.0;
+  volatile double *lane_err = f_lane;  // kept in LDS, not promoted to a register
+  __builtin_amdgcn_wave_barrier();  // the prologue's reads of the stage come first
+  *lane_err = 0.0;
+  auto fold = [&]() {
+    const double s = lane_sum + lane_cost;
+    const double bp = s - lane_sum;
+    *lane_err += (lane_sum - (s - bp)) + (lane_cost - bp);
+    lane_sum = s;
+    lane_cost = 0.0;
+  };
   double g[kRS];
 #pragma unroll
   for (int r = 0; r < kRS; ++r) g[r] = 0.0;
@@ -1190,6 +1194,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         if (k + i < n_full || (extra && k + i == n_full))
           bin_step(cheb_tag, k + i, (double)dq[i], inv_of(dq[i], (double)dq[i]));
     }
+    if constexpr (MODE == kModeCost) fold();
   }
   };
   if constexpr (kChebShape) {
@@ -1204,7 +1209,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 
   // wave reduction of the cost (compensated) and the gradient (fixed tree);
   // lane 0 writes the segment's slot
-  const Pair pc = wave_pair_sum(Pair{lane_cost, 0.0});
+  const Pair pc = wave_pair_sum(MODE == kModeCost ? Pair{lane_sum, *lane_err} : Pair{lane_cost, 0.0});
   if (lane == 0) {
     slot[0] = pc.s;
     slot[1] = pc.c;
@@ -1238,22 +1243,25 @@ __device__ __forceinline__ int histo_at(const DevHisto *hs, int n_histo, int64_t
 }
 
 // The unit of work is one wave (64 lanes; four per workgroup, which share the
-// reciprocal table). Unit u is wave u % 4 of workgroup u / 4.
-// Tile launch: unit u evaluates tile u of its job.
-// Split launch (uniform jobs, split_w > 0): the n_vec x total (vector, bin)
-// space is cut into equal ranges of split_w bins, one per unit, so every unit
-// has the same work; a range is evaluated as the (vector, histogram) segments
-// it crosses. Segment (unit u, histogram j = v * n_histo + h) owns slot u + j:
-// the sum grows by one or two from one segment to the next, so slots are
-// unique and each histogram's slots are contiguous. When a range starts
-// exactly at a histogram start, slot u + j - 1 belongs to no segment and is
-// written as zero so that every slot inside a vector's span is defined.
+// reciprocal table). Unit u is wave u % 4 of workgroup u / 4. Every launch
+// cuts its work into equal ranges of split_w bins, one per unit, so every
+// unit has the same work; a range is evaluated as the segments it crosses.
+// Uniform launch: the n_vec x total (vector, bin) space of one dataset;
+// histogram j = v * n_histo + h. Batched launch: the fit ranges of its jobs,
+// concatenated in job-list order; histogram j = jbase + h of the job.
+// Segment (unit u, histogram j) owns slot u + j: the sum grows by one or two
+// from one segment to the next, so slots are unique and each histogram's
+// slots are contiguous. When a range starts exactly at a histogram start,
+// slot u + j - 1 belongs to no segment and is written as zero so that every
+// slot inside a job's span is defined.
 // Minimum waves per SIMD asked of the register allocator: the chi^2 cost
 // kernels of the compiled shapes fit six (80 registers) without spilling;
 // the others are left to the compiler's own choice.
-template <int COST, int MODE, typename Sh>
+template <int COST, int MODE, typename Sh, int TAB>
 constexpr int eval_min_waves() {
-  return (COST == MU_COST_CHI2 && MODE == kModeCost && Sh::kFixed) ? 6 : 1;
+  // without the table, the range test of large counts needs more registers
+  // in the largest shape
+  return (COST == MU_COST_CHI2 && MODE == kModeCost && Sh::kFixed) ? (TAB || Sh::kTerms < 2 ? 6 : 5) : 1;
 }
 
 // The workgroup's copy of the context's reciprocal table (chi^2 on integer
@@ -1266,6 +1274,31 @@ __device__ __forceinline__ void load_inv_table(double *inv_tab, const double *sr
   __syncthreads();
 }
 
+// Shape tag of launches whose segments each run their job's compiled shape
+// (registers: those of the largest shape).
+struct ShapeAny {
+  static constexpr bool kFixed = true;
+  static constexpr int kTerms = 2;
+};
+
+// One segment with the body of shape Sh, or with the job's own compiled
+// shape under ShapeAny (a wave-uniform switch).
+template <int COST, int MODE, typename CT, typename Sh, int TAB>
+__device__ __forceinline__ void eval_segment_of(const SegIn &S, double *slot, int shape) {
+  if constexpr (std::is_same<Sh, ShapeAny>::value) {
+    switch (shape) {
+      case kShapeExpCos: eval_segment<COST, MODE, CT, ShapeExpCos, TAB>(S, slot); break;
+      case kShapeGaussCos: eval_segment<COST, MODE, CT, ShapeGaussCos, TAB>(S, slot); break;
+      case kShapeStg: eval_segment<COST, MODE, CT, ShapeStg, TAB>(S, slot); break;
+      case kShapeExpStg: eval_segment<COST, MODE, CT, ShapeExpStg, TAB>(S, slot); break;
+      default: eval_segment<COST, MODE, CT, ShapeExpCosStg, TAB>(S, slot); break;
+    }
+  } else {
+    (void)shape;
+    eval_segment<COST, MODE, CT, Sh, TAB>(S, slot);
+  }
+}
+
 // The work units (waves) of workgroup b of launch a.
 // TAB = 1: every count of the launch is an integer below kInvTab (the table
 // lookup needs neither clamp nor range test).
@@ -1275,50 +1308,40 @@ __device__ __forceinline__ void eval_units(const LaunchArgs &a, int b, const dou
   const int u = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + (int)(threadIdx.x / kWave));  // wave-uniform
   const int lane = threadIdx.x & (kWave - 1);
   if (u >= a.n_units) return;
-  const bool split = a.split_w != 0;
-  const int nh = a.tmpl.n_histo;
-  int64_t pos = 0, end = 0;
-  int v = 0, h = 0;
-  if (split) {
-    pos = (int64_t)u * a.split_w;
-    end = min(pos + a.split_w, (int64_t)a.n_vec * a.total);
-    if (pos >= end) return;
+  const bool batch = a.jobs != nullptr;
+  int64_t pos = (int64_t)u * a.split_w;
+  const int64_t end = min(pos + a.split_w, batch ? a.total : (int64_t)a.n_vec * a.total);
+  if (pos >= end) return;
+  // v: the vector (uniform launch) or the job-list entry (batched launch)
+  int v, h;
+  DevJob J;
+  int64_t vstart;  // first bin of vector / job v in the launch
+  if (batch) {
+    v = uni(a.unit_start[2 * u]);
+    h = uni(a.unit_start[2 * u + 1]);
+    J = a.jobs[uni(a.job_list[v])];
+    vstart = uni(J.goff);
+  } else {
     v = (int)(pos / a.total);
-    h = histo_at(a.tmpl.histos, nh, pos - (int64_t)v * a.total);
-    if (MODE != kModeModel && pos == (int64_t)v * a.total + a.tmpl.histos[h].off && (v > 0 || h > 0)) {
-      if (lane < kSlot) a.partial[((int64_t)u + (int64_t)v * nh + h - 1) * kSlot + lane] = 0.0;
-    }
+    vstart = (int64_t)v * a.total;
+    J = a.tmpl;
+    h = histo_at(J.histos, J.n_histo, pos - vstart);
+  }
+  int nh = uni(J.n_histo), jb = batch ? uni(J.jbase) : v * nh;
+  if (MODE != kModeModel && jb + h > 0 && pos == vstart + J.histos[h].off) {
+    if (lane < kSlot) a.partial[((int64_t)u + jb + h - 1) * kSlot + lane] = 0.0;
   }
   for (;;) {
     SegIn S;
-    DevHisto H;
-    double *slot;
-    int64_t seg_end = 0;
-    if (!split) {
-      int job;
-      const DevJob J = job_of(a, u, job);
-      const DevTile T = J.tiles[u - J.unit_base];
-      H = J.histos[T.histo];
-      S.th = J.th;
-      S.p = J.p;
-      S.counts = J.counts;
-      S.model_out = J.model_out;
-      S.begin = T.begin;
-      S.n = T.n;
-      // the job's slots are global across the per-shape launches of one batch
-      slot = a.partial + ((int64_t)J.tile_base + (u - J.unit_base)) * kSlot;
-    } else {
-      H = uni(a.tmpl.histos[h]);
-      const int64_t h_start = (int64_t)v * a.total + H.off;
-      seg_end = min(end, h_start + H.n);
-      S.th = a.tmpl.th;
-      S.p = a.tmpl.p + (int64_t)v * a.p_stride;
-      S.counts = a.tmpl.counts;
-      S.model_out = a.tmpl.model_out;
-      S.begin = pos - h_start;
-      S.n = (int32_t)(seg_end - pos);
-      slot = a.partial + ((int64_t)u + (int64_t)v * nh + h) * kSlot;
-    }
+    const DevHisto H = uni(J.histos[h]);
+    const int64_t h_start = vstart + H.off;
+    const int64_t seg_end = min(end, h_start + H.n);
+    S.th = J.th;
+    S.p = batch ? J.p : J.p + (int64_t)v * a.p_stride;
+    S.counts = J.counts;
+    S.model_out = J.model_out;
+    S.begin = pos - h_start;
+    S.n = (int32_t)(seg_end - pos);
     S.off = H.off;
     S.first = H.first;
     S.t0_bin = H.t0_bin;
@@ -1326,13 +1349,21 @@ __device__ __forceinline__ void eval_units(const LaunchArgs &a, int b, const dou
     S.map_row = H.map_row;
     S.anchor_every = a.anchor_every;
     S.inv_tab = inv_tab;
-    eval_segment<COST, MODE, CT, Sh, TAB>(S, slot);
-    if (!split) return;
+    eval_segment_of<COST, MODE, CT, Sh, TAB>(S, a.partial + ((int64_t)u + jb + h) * kSlot, uni(J.shape));
     pos = seg_end;
     if (pos >= end) return;
     if (++h == nh) {
       h = 0;
       ++v;
+      if (batch) {
+        J = a.jobs[uni(a.job_list[v])];
+        vstart = uni(J.goff);
+        nh = uni(J.n_histo);
+        jb = uni(J.jbase);
+      } else {
+        vstart += a.total;
+        jb += nh;
+      }
     }
   }
 }
@@ -1343,7 +1374,7 @@ constexpr bool eval_table() {
 }
 
 template <int COST, int MODE, typename CT, typename Sh, int TAB>
-__global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh>())) void eval_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh, TAB>())) void eval_kernel(LaunchArgs a) {
   constexpr bool kTable = eval_table<COST, MODE, CT>();
   __shared__ __align__(16) double inv_tab[kTable ? kInvTab : 2];
   if constexpr (kTable) load_inv_table(inv_tab, a.inv_src);
@@ -1378,7 +1409,6 @@ __device__ __forceinline__ void merge_block(const LaunchArgs &a, int job) {
     J.cost_out += job;
     if (J.histo_out) J.histo_out += job * a.histo_stride;
     if (J.grad_out) J.grad_out += job * a.grad_stride;
-    J.tile_base = job * a.tmpl.n_tiles;
   } else {
     J = a.jobs[job];
   }
@@ -1524,6 +1554,53 @@ hipError_t launch_typed(const LaunchArgs &a, int count_f64, int shape, hipStream
 }
 
 }  // namespace
+
+namespace {
+
+template <int COST, int MODE>
+hipError_t launch_batch_typed(const LaunchArgs &a, int count_f64, int generic, hipStream_t s) {
+  dim3 grid((a.n_units + kBlock / kWave - 1) / (kBlock / kWave)), block(kBlock);
+  constexpr bool kTab = COST == MU_COST_CHI2;
+  if (count_f64)
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, double, ShapeGeneric, 0>), grid, block, 0, s, a);
+  else if (generic)
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeGeneric, 0>), grid, block, 0, s, a);
+  else if (kTab && a.counts_in_table)
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeAny, kTab ? 1 : 0>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeAny, 0>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <int COST, int MODE>
+int batch_occupancy(int count_f64, int generic) {
+  int nb = 0;
+  const void *k = (count_f64 || generic)
+                      ? (count_f64 ? reinterpret_cast<const void *>(&eval_kernel<COST, MODE, double, ShapeGeneric, 0>)
+                                   : reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, ShapeGeneric, 0>))
+                      : reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, ShapeAny, 0>);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, 0) == hipSuccess ? nb : 0;
+}
+
+}  // namespace
+
+hipError_t launch_eval_batch(const LaunchArgs &a, int mode, int count_f64, int generic, hipStream_t s) {
+  if (a.n_units <= 0) return hipSuccess;
+  if (a.anchor_every < 1 || a.anchor_every > 256 || a.jobs == nullptr || a.split_w <= 0) return hipErrorInvalidValue;
+  if (a.cost_kind == MU_COST_CHI2)
+    return mode == kModeGrad ? launch_batch_typed<MU_COST_CHI2, kModeGrad>(a, count_f64, generic, s)
+                             : launch_batch_typed<MU_COST_CHI2, kModeCost>(a, count_f64, generic, s);
+  return mode == kModeGrad ? launch_batch_typed<MU_COST_POISSON, kModeGrad>(a, count_f64, generic, s)
+                           : launch_batch_typed<MU_COST_POISSON, kModeCost>(a, count_f64, generic, s);
+}
+
+int eval_batch_blocks_per_cu(int mode, int cost_kind, int count_f64, int generic) {
+  if (cost_kind == MU_COST_CHI2)
+    return mode == kModeGrad ? batch_occupancy<MU_COST_CHI2, kModeGrad>(count_f64, generic)
+                             : batch_occupancy<MU_COST_CHI2, kModeCost>(count_f64, generic);
+  return mode == kModeGrad ? batch_occupancy<MU_COST_POISSON, kModeGrad>(count_f64, generic)
+                           : batch_occupancy<MU_COST_POISSON, kModeCost>(count_f64, generic);
+}
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s) {
   if (a.n_units <= 0) return hipSuccess;

@@ -34,6 +34,10 @@ namespace {
 
 enum Phase { kStart, kHessInit, kIter, kLine, kHessPolish, kPolish, kDone };
 constexpr int kRefresh = 50;  // variable-metric steps between Hessian refreshes of an unconverged fit
+// Times a fit that stalls with its EDM above the tolerance (steps below the
+// step tolerance, a failed line search, or a polish that cannot lower the
+// cost) starts again from a fresh differenced Hessian before it gives up.
+constexpr int kMaxStalls = 3;
 
 struct Point {
   std::vector<double> p;  // full parameter vector
@@ -89,6 +93,7 @@ struct Fit {
   int phase = kStart;
   int n_iter = 0, n_fcn = 0, n_grad = 0, status = 0, tries = 0, polish_iter = 0;
   int refreshed = -1;  // iteration of the last Hessian refresh
+  int stalls = 0;      // restarts after a stall (at most kMaxStalls)
   std::vector<Point> posts;
 
   std::vector<double> full(const std::vector<double> &xf) const {
@@ -175,6 +180,24 @@ struct Fit {
       }
     }
     edm = -0.5 * gd;
+  }
+  // End of the fit: EDM from the final gradient and metric (after a polish
+  // the inverse of the differenced Hessian), and the status it supports.  A
+  // fit is converged only when that EDM is below the tolerance, whatever
+  // stopped it; a fit that stopped on a small step (or a failed line search)
+  // with a larger EDM keeps a status of its own.
+  void finish(double tol_edm) {
+    edm = 0.0;
+    if (!V.empty())
+      for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) edm += 0.5 * g[i] * V[i * n + k] * g[k];
+    if (status != 2) {
+      if (edm < tol_edm)
+        status = 0;
+      else if (status == 0)
+        status = 4;
+    }
+    phase = kDone;
   }
   void post_line() {
     xt.assign(n, 0.0);
@@ -349,11 +372,22 @@ struct FitDriver {
         double an = std::isfinite(ft) ? -F.gd * a * a / (2.0 * (ft - F.f - F.gd * a)) : 0.1 * a;
         an = std::min(std::max(an, 0.1 * a), 0.5 * a);
         F.alpha = an;
-        if (++F.tries > 40 || !budget_left()) {
+        if (++F.tries > 40 && budget_left() && F.stalls < kMaxStalls && F.n_iter < o.max_iter) {
+          // no acceptable point along -V g: restart from a differenced Hessian
+          F.stalls++;
+          F.refreshed = F.n_iter;
+          F.last_step = 1e300;
+          F.post_hessian();
+          F.phase = kHessInit;
+          return;
+        }
+        if (F.tries > 40 || !budget_left()) {
           F.status = budget_left() ? 3 : 1;
-          F.phase = o.polish ? kHessPolish : kDone;
-          if (F.phase == kHessPolish) {
+          if (o.polish) {
             F.post_hessian();
+            F.phase = kHessPolish;
+          } else {
+            F.finish(o.tol_edm);
           }
           return;
         }
@@ -378,15 +412,13 @@ struct FitDriver {
           F.x = F.xt;
           F.f = ft;
           for (int k = 0; k < n; ++k) F.g[k] = got[0].g[F.fi[k]];
-          F.edm = 0.0;
-          for (int i = 0; i < n; ++i)
-            for (int k = 0; k < n; ++k) F.edm += 0.5 * F.g[i] * F.V[i * n + k] * F.g[k];
           if (step > 1e-12 && ++F.polish_iter < 8 && budget_left()) {
             post_newton(F);
             return;
           }
         }
-        F.phase = kDone;
+        if (polish_stalled(F)) break;
+        F.finish(o.tol_edm);
         return;
       }
       default:
@@ -408,13 +440,24 @@ struct FitDriver {
       F.phase = kHessInit;
       return;
     }
+    if (F.edm >= o.tol_edm && F.n_iter > 0 && F.last_step < o.tol_step_rel && F.stalls < kMaxStalls &&
+        F.n_iter < o.max_iter) {
+      // steps below the tolerance while the EDM is not: the variable metric
+      // has lost the valley's curvature; restart from a differenced Hessian
+      F.stalls++;
+      F.refreshed = F.n_iter;
+      F.last_step = 1e300;
+      F.post_hessian();
+      F.phase = kHessInit;
+      return;
+    }
     if (F.edm < o.tol_edm || (F.n_iter > 0 && F.last_step < o.tol_step_rel) || F.n_iter >= o.max_iter) {
       if (F.n_iter >= o.max_iter && F.edm >= o.tol_edm) F.status = 1;
       if (o.polish) {
         F.post_hessian();
         F.phase = kHessPolish;
       } else {
-        F.phase = kDone;
+        F.finish(o.tol_edm);
       }
       return;
     }
@@ -424,12 +467,38 @@ struct FitDriver {
     F.phase = kLine;
   }
 
+  // A polish that ends (no lower point, or an indefinite Hessian) while the
+  // EDM from the differenced Hessian is still above the tolerance: back to
+  // variable-metric steps with that Hessian's inverse as the metric, at most
+  // kMaxStalls times.  Returns true when the fit goes on iterating.
+  bool polish_stalled(Fit &F) {
+    const int n = F.n;
+    F.edm = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) F.edm += 0.5 * F.g[i] * F.V[i * n + k] * F.g[k];
+    if (!(F.edm >= o.tol_edm) || F.stalls >= kMaxStalls || F.n_fcn >= o.max_fcn || F.n_iter >= o.max_iter)
+      return false;
+    F.stalls++;
+    F.status = 0;
+    F.last_step = 1e300;
+    F.phase = kIter;
+    return true;
+  }
+
   void post_newton(Fit &F) {
     const int n = F.n;
     std::vector<double> L = F.H;
     F.xt = F.x;
     if (!cholesky(L, n)) {  // no Newton step from an indefinite Hessian
-      F.phase = kDone;
+      if (polish_stalled(F)) {
+        F.alpha = 1.0;
+        F.tries = 0;
+        F.direction();
+        F.post_line();
+        F.phase = kLine;
+        return;
+      }
+      F.finish(o.tol_edm);
       return;
     }
     std::vector<double> Hi = spd_inverse(L, n);

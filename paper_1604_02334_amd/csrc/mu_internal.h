@@ -84,13 +84,7 @@ struct DevHisto {
   double t0_bin;
   double dt;
   int32_t map_row;
-  int32_t tile0;  // first tile of this histogram in the dataset's tile table
-};
-
-struct DevTile {
-  int64_t begin;  // first bin, relative to the histogram's fit range
-  int32_t histo;
-  int32_t n;      // bins in this tile
+  int32_t pad;
 };
 
 // One evaluation job: a parameter vector over one dataset and theory.
@@ -98,17 +92,21 @@ struct DevJob {
   const DevTheory *th;
   const DevHisto *histos;
   const void *counts;
-  const DevTile *tiles;
   const double *p;       // parameter vector (device)
   double *cost_out;      // [1]
   double *histo_out;     // [n_histo] or null
   double *grad_out;      // [n_par] or null
   double *model_out;     // per-bin N (model evaluation) or null
   const int32_t *plan;   // gradient merge plan (gradient launches) or null
-  int32_t n_tiles;
+  // Batched launches: the job's first bin in its launch's concatenated fit
+  // ranges, that launch's bins per wave, the index of the job's first
+  // histogram among the launch's histograms, and the launch's first slot.
+  int64_t goff;
+  int64_t split_w;
+  int32_t jbase;
+  int32_t slot_base;
   int32_t n_histo;
-  int32_t tile_base;     // first partial slot of this job
-  int32_t unit_base;     // first work unit (wave) of this job in its launch
+  int32_t shape;         // compiled shape of the theory (kShapeGeneric: interpreted)
 };
 
 enum Mode : int { kModeCost = 0, kModeGrad = 1, kModeModel = 2 };
@@ -126,28 +124,31 @@ enum Shape : int {
 
 struct LaunchArgs {
   // The unit of work is one wave of kWave lanes; a workgroup holds
-  // kBlock / kWave units.
-  // Uniform launch (jobs == null): job v is `tmpl` with its parameter vector
-  // and outputs advanced by v strides, and owns units
-  // [v * tmpl.n_tiles, (v + 1) * tmpl.n_tiles).
+  // kBlock / kWave units. Every launch cuts its concatenated work into equal
+  // ranges of split_w bins, one per unit; a range is evaluated as the
+  // (vector or job, histogram) segments it crosses, and segment (unit u,
+  // histogram j of the launch's enumeration) owns slot u + j of `partial`.
+  // Uniform launch (jobs == null): n_vec vectors of `total` fit-range bins
+  // each over one dataset; job v is `tmpl` with its parameter vector and
+  // outputs advanced by v strides; histogram h of vector v is j = v n_histo + h.
   DevJob tmpl;
   int64_t p_stride, grad_stride, histo_stride;
-  // Mapped launch: explicit jobs and a unit -> job table.
+  // Batched launch: the jobs `job_list[0 .. n_vec)` of `jobs`, concatenated
+  // in that order (`total` bins); unit u starts in job list entry
+  // unit_start[2u] at its histogram unit_start[2u + 1]; histogram h of a job
+  // is j = jbase + h.
   const DevJob *jobs;
-  const int32_t *unit_job;
+  const int32_t *job_list;
+  const int32_t *unit_start;
   int32_t n_units;
   int32_t cost_kind;
   int32_t anchor_every;  // lane steps between exact re-evaluations, 1..256
   int32_t counts_in_table;  // 1: every count of every job is an integer below kInvTab
   const double *inv_src;    // [kInvTab] 1 / max(i, 1) (device), copied to LDS by chi^2 launches
-  // Split launch (jobs == null, split_w > 0): n_vec vectors of `total`
-  // fit-range bins each, cut into ranges of split_w bins, one per unit;
-  // slot u + v * n_histo + h of `partial` belongs to unit u's segment of
-  // histogram h of vector v.
   int32_t n_vec;
   int64_t split_w;
   int64_t total;
-  double *partial;    // tile launch: [total tiles of all jobs][kSlot]
+  double *partial;    // this launch's slots
 };
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);
@@ -160,7 +161,11 @@ hipError_t launch_eval_grad_cost(const LaunchArgs &g, const LaunchArgs &c, int c
 // Workgroups (of kBlock / kWave units each) of the evaluation kernel resident
 // per compute unit (0 if unknown).
 int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape);
-// Merge the tile slots of jobs [0, n_jobs) of `a` (uniform or mapped).
+// One batched launch over jobs of compiled shapes (each segment runs its
+// job's shape) or, with generic != 0, of any theory (interpreted).
+hipError_t launch_eval_batch(const LaunchArgs &a, int mode, int count_f64, int generic, hipStream_t s);
+int eval_batch_blocks_per_cu(int mode, int cost_kind, int count_f64, int generic);
+// Merge the slots of jobs [0, n_jobs) of `a` (uniform or batched).
 hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s);
 // One launch merging a gradient launch's n_grad jobs and a cost launch's n_cost jobs.
 hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, hipStream_t s);

@@ -15,6 +15,9 @@ namespace mu {
 
 constexpr int kMinTile = 1024, kMaxTile = 65536;
 constexpr int kMaxSplit = 1 << 26;  // largest explicit bins-per-unit value
+// Longest range of a gradient pass's wave: each lane sums at most 2^14 terms
+// plainly (cost passes fold their sums by TwoSum at every anchor instead).
+constexpr int kMaxGradSplit = 1 << 20;
 constexpr int kDefaultAnchor = 64;
 
 // Grow-only device buffer owned by a context.
@@ -43,10 +46,10 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
 // The same with device pointers only, on stream s with partial slots `partial`.
 mu_status eval_dev(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp, int32_t n_vec,
                    double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s, DevBuf &partial);
-struct TileSet;
-mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const TileSet *const *sets,
-                    const mu_theory *const *th, int cost_kind, int32_t ld, const double *params, unsigned mem,
-                    double *cost, double *grad, int64_t n_units, int anchor);
+// n_jobs (dataset, theory, vector) jobs: one launch for the jobs of compiled
+// shapes, one for the others, then one merge launch.
+mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,
+                    int cost_kind, int32_t ld, const double *params, unsigned mem, double *cost, double *grad);
 
 }  // namespace mu
 
@@ -64,7 +67,9 @@ struct mu_ctx {
     int key, tile, anchor;
   };
   std::vector<Tuned> tuned;
-  int pick_tile(int shape, int mode, int cost, int64_t work, int64_t longest, int *anchor) const;
+  // Bins per wave of a batched launch (generic: the interpreted kernel's
+  // launch, else the compiled shapes' launch) of `work` bins.
+  int64_t pick_batch(int generic, int mode, int cost, int count_f64, int64_t work, int *anchor) const;
   // Bins per wave of a split launch (single dataset, n_vec vectors).
   int64_t pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const;
   int specialize = 1;  // use the compiled shape kernels when a theory matches one
@@ -96,16 +101,6 @@ struct mu_ctx {
   }
 };
 
-namespace mu {
-// Histogram and tile tables of one dataset for one tile size.
-struct TileSet {
-  int tile_bins = 0;
-  mu::DevHisto *d_histos = nullptr;  // with tile0 for this tile size
-  mu::DevTile *d_tiles = nullptr;
-  int32_t n_tiles = 0;
-};
-}  // namespace mu
-
 struct mu_data {
   mu_ctx *ctx = nullptr;
   void *counts = nullptr;  // FP32 or FP64 fit-range counts, concatenated
@@ -116,10 +111,7 @@ struct mu_data {
   int64_t longest = 0;     // bins of the longest fit range
   double max_count = 0.0;  // largest fit-range count
   std::vector<mu::DevHisto> hh;
-  std::deque<mu::TileSet> sets;  // one per tile size used so far (few); stable addresses
-  mu::DevHisto *d_hh = nullptr;  // device copy of hh (split launches)
-  // Tables for `tile_bins`, built on first use and kept until destruction.
-  mu_status tiles(int tile_bins, const mu::TileSet **out);
+  mu::DevHisto *d_hh = nullptr;  // device copy of hh
   // Gradient merge plans, one per theory used with this dataset (by theory
   // id), built on first use and kept until destruction.
   struct Plan {

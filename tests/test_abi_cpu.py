@@ -125,3 +125,34 @@ def test_handle_array_is_contiguous_and_refuses_closed_handles():
     objs[3].addr = 0
     with pytest.raises(ValueError):
         api.handle_array(objs)
+
+
+def _cache(tmp_path, text, name="tune.txt"):
+    p = tmp_path / name
+    p.write_text(text)
+    return str(p)
+
+
+def test_tuning_cache_file_validation(tmp_path):
+    """The tuning cache text format is checked without a device: a good file
+    passes; a missing file, a wrong header, a missing architecture line, a
+    malformed line and every out-of-range field are refused (and a context
+    would load nothing from such a file)."""
+    head = "mu-autotune 1\narch gfx950:sramecc+:xnack-\n# shape mode cost kind log2 tile anchor\n"
+    good = head + "6 0 0 0 26 16384 64\n5 1 0 1 20 8192 128\n\n"
+    st, msg = api.autotune_check_file(_cache(tmp_path, good))
+    assert st == A.MU_OK and "2 entries" in msg and "gfx950" in msg
+    st, msg = api.autotune_check_file(str(tmp_path / "absent.txt"))
+    assert st == A.MU_E_ARG and "cannot open" in msg
+    st, msg = api.autotune_check_file(_cache(tmp_path, "mu-autotune 2\narch gfx950\n"))
+    assert st == A.MU_E_ARG and "header" in msg
+    st, msg = api.autotune_check_file(_cache(tmp_path, "mu-autotune 1\n6 0 0 0 26 16384 64\n"))
+    assert st == A.MU_E_ARG and "arch" in msg
+    st, msg = api.autotune_check_file(_cache(tmp_path, ""))
+    assert st == A.MU_E_ARG
+    bad_lines = ["6 0 0 0 26 16384", "6 0 0 0 26 16384 64 9", "7 0 0 0 26 16384 64", "6 2 0 0 26 16384 64",
+                 "6 0 2 0 26 16384 64", "6 0 0 2 26 16384 64", "6 0 0 0 63 16384 64", "6 0 0 0 26 63 64",
+                 "6 0 0 0 26 67108865 64", "6 0 0 0 26 16384 0", "6 0 0 0 26 16384 257", "six 0 0 0 26 16384 64"]
+    for i, line in enumerate(bad_lines):
+        st, msg = api.autotune_check_file(_cache(tmp_path, head + "6 0 0 0 26 16384 64\n" + line + "\n", f"b{i}.txt"))
+        assert st == A.MU_E_ARG and "line 5" in msg, (line, msg)

@@ -69,15 +69,37 @@ def test_fit_matches_linear_least_squares(ctx):
     np.testing.assert_array_equal(p[0][2:], start[2:])
 
 
+def _same_minimum(pa, pb, cov, tol=1e-6):
+    """Two fits of one dataset agree when every parameter differs by at most
+    tol * max(|p_k|, sigma_k) (sigma from the covariance 2V).  Where the
+    correlation matrix has condition above 1e6 (a parameter combination the
+    data barely determine) the test is made along the eigen-directions of
+    the covariance in those scaled units: each direction whose standard
+    deviation is at most 1 (determined to better than the parameter scale)
+    must agree to tol; looser directions are not compared.  Returns (ok,
+    worst ratio, ill-conditioned)."""
+    sig = np.sqrt(np.abs(np.diag(cov)))
+    scale = np.maximum(np.abs(pa), sig)
+    d = (pa - pb) / scale
+    corr = cov / np.outer(np.where(sig > 0, sig, 1.0), np.where(sig > 0, sig, 1.0))
+    ill = not np.all(np.isfinite(corr)) or np.linalg.cond(corr) > 1e6
+    if not ill:
+        return bool(np.all(np.abs(d) <= tol)), float(np.max(np.abs(d))), False
+    w, Q = np.linalg.eigh(cov / np.outer(scale, scale))
+    y = Q.T @ d
+    sel = np.sqrt(np.maximum(w, 0.0)) <= 1.0
+    worst = float(np.max(np.abs(y[sel]))) if np.any(sel) else 0.0
+    return worst <= tol, worst, True
+
+
 def test_batched_and_plain_paths_agree(ctx):
     """Uneven independent datasets: the batched path (one launch per round,
     analytic gradients) and the plain path (one launch per cost evaluation,
-    central differences) reach the same minimum; the plain one needs many
-    more evaluations. A set whose covariance is degenerate (correlation
-    matrix condition number above 1e6: some parameter combination is not
-    determined by the data) has no well-defined minimum point, only a
-    well-defined minimum cost; there the two costs agree to 1e-2 (a hundredth
-    of the change of 1 that marks one standard deviation)."""
+    central differences) reach the same minimum within 1e-6 of
+    max(|p|, sigma) (along the determined directions where the covariance is
+    nearly degenerate); the plain one needs many more evaluations.  Every
+    fit must converge (EDM below tolerance) unless its covariance is
+    degenerate; the exceptions are counted by cause."""
     _say("batched vs plain")
     cfg = synth.config_c4(n_sets=12, lo_exp=11, hi_exp=13)
     rng = cfg["rng"]
@@ -91,19 +113,20 @@ def test_batched_and_plain_paths_agree(ctx):
         start[j, :s["start"].size] = s["start"]
     pb, covb, rb = api.fit_batch(ctx, ds, ths, start)
     pp, covp, rp = api.fit_batch(ctx, ds, ths, start, analytic_grad=False, batched=False)
+    causes = {"compared": 0, "compared_degenerate": 0, "unconverged_degenerate": 0}
     for j, s in enumerate(sets):
         n = s["start"].size
-        sig = np.sqrt(np.abs(np.diag(covb[j]))[:n])
+        ok, worst, ill = _same_minimum(pb[j, :n], pp[j, :n], covb[j][:n, :n])
         if rb[j]["status"] != 0 or rp[j]["status"] != 0:
+            # only a fit in a degenerate valley may stay unconverged
+            assert ill, (j, s["family"], rb[j], rp[j])
+            causes["unconverged_degenerate"] += 1
             continue
-        corr = covb[j][:n, :n] / np.outer(sig, sig)
-        if np.linalg.cond(corr) > 1e6:
-            assert abs(rb[j]["cost"] - rp[j]["cost"]) <= 1e-2, (j, s["family"], rb[j], rp[j])
-            continue
-        ok, worst = _agree(pb[j, :n], pp[j, :n], sig, tol=1e-5)
-        assert ok, (j, s["family"], worst)
+        causes["compared_degenerate" if ill else "compared"] += 1
+        assert ok, (j, s["family"], worst, pb[j, :n], pp[j, :n])
+    print("[fits]", causes, flush=True)
+    assert causes["compared"] >= len(sets) - 2
     assert sum(r["n_fcn"] for r in rp) > sum(r["n_fcn"] for r in rb)
-    assert sum(r["status"] == 0 for r in rb) >= len(sets) - 1
 
 
 def test_fit_c2_shape_reduced(ctx):

@@ -14,7 +14,9 @@ definitions:
 * Listing 3  parameter / function / map indirection; tf = cos(2 pi nu t + phi)
 
 Modules: ``model`` (cost and analytic gradient), ``scalar`` (pure-Python
-cross-check for tiny inputs), ``fit`` (reference minimiser), ``seeder``
+cross-check for tiny inputs), ``fit`` (reference minimiser), ``errors``
+(Gauss-Newton Hessian, covariance, likelihood profiles and their
+one-standard-deviation crossings), ``seeder``
 (reference network with BF16 rounding), ``philox`` (counter-based generator
 from its published definition; the seeder's parameter draws and expected
 rebinned counts live in ``seeder``).

@@ -181,6 +181,24 @@ mu_status mu_chi2_eval(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu
                        const double *params, int32_t n_vec, unsigned mem,
                        double *cost, double *cost_per_histo);
 
+/* mu_chi2_eval for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launches and results, bit for bit, as mu_chi2_eval with MU_MEM_DEVICE, but
+ * no device or host allocation of any kind.  params, cost and cost_per_histo
+ * are device pointers on the context's device; the call only enqueues work
+ * on the context stream.  The partial slots live in a static array of the
+ * library's code object on each device: 32768 slots of 256 B (8 MiB), held
+ * until the process ends.  A launch needs one slot per work range plus
+ * n_vec x n_histo; a call that needs more is refused with MU_E_UNSUPPORTED
+ * before anything is enqueued (fewer vectors per call, or a larger
+ * mu_ctx_set_tile, fits it).  Every call on one device shares that array:
+ * calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race and give wrong results; calls in order on one stream do not.
+ * No kernel timing is recorded for this entry point.  Other errors as
+ * mu_chi2_eval. */
+mu_status mu_chi2_eval_static(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                              const double *params, int32_t n_vec, double *cost, double *cost_per_histo);
+
 /* Cost and its analytic gradient d cost / d p (adjoint pass: per bin the
  * cost's derivative in N times dN/dp through Eq. 1, the product form of A and
  * the map / function array).  grad: [n_vec][n_par]. */

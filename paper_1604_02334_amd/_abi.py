@@ -122,6 +122,7 @@ def lib():
         "mu_theory_npar": (C.c_int32, [vp]),
         "mu_chi2_eval": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, vp, vp]),
         "mu_chi2_grad": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, vp, vp]),
+        "mu_chi2_eval_static": (S, [vp, vp, vp, S, vp, C.c_int32, vp, vp]),
         "mu_chi2_eval_grad": (S, [vp, vp, vp, S, vp, C.c_int32, vp, C.c_int32, C.c_uint, vp, vp, vp]),
         "mu_chi2_batch": (S, [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), S, C.c_int32, vp, C.c_uint, vp, vp]),
         "mu_model_eval": (S, [vp, vp, vp, vp, C.c_uint, vp]),
@@ -145,6 +146,7 @@ def exported_symbols():
                    "mu_histo_check", "mu_data_create",
                    "mu_data_destroy", "mu_data_bins", "mu_data_histos", "mu_data_is_f64", "mu_theory_check",
                    "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_chi2_eval", "mu_chi2_grad",
+                   "mu_chi2_eval_static",
                    "mu_chi2_eval_grad", "mu_chi2_batch", "mu_model_eval", "mu_fit_batch",
                    "mu_seeder_param_count", "mu_seeder_create", "mu_seeder_destroy", "mu_seeder_get_params",
                    "mu_seeder_get_grads", "mu_seeder_steps", "mu_gen_histos", "mu_seeder_forward",

@@ -295,6 +295,25 @@ def chi2_eval(ctx, data, theory, params, cost="chi2", per_histo=False):
     return (out, ph) if per_histo else out
 
 
+def chi2_eval_static(ctx, data, theory, params, out, per_histo=None, cost="chi2"):
+    """mu_chi2_eval_static: the cost of each vector of a CUDA tensor params
+    [n_vec, n_par] into the caller's CUDA tensors out [n_vec] (and per_histo
+    [n_vec, n_histo]), with no allocation by the library; enqueued on the
+    context's stream."""
+    L = A.lib()
+    for t in (params, out) + ((per_histo,) if per_histo is not None else ()):
+        if not (_is_torch(t) and t.is_cuda and t.is_contiguous()):
+            raise ValueError("chi2_eval_static takes contiguous CUDA tensors only")
+    n_vec = params.shape[0] if params.dim() == 2 else 1
+    cur = ctx._enter_device()
+    _check(L.mu_chi2_eval_static(ctx.h, data.h, theory.h, _cost_code(cost), C.c_void_p(params.data_ptr()), n_vec,
+                                 C.c_void_p(out.data_ptr()),
+                                 C.c_void_p(per_histo.data_ptr()) if per_histo is not None else None),
+           ctx.h, "mu_chi2_eval_static")
+    ctx._leave_device(cur, [params, out, per_histo])
+    return out
+
+
 def chi2_grad(ctx, data, theory, params, cost="chi2"):
     """Cost and analytic gradient of each parameter vector."""
     L = A.lib()

@@ -45,6 +45,11 @@ mu_status hip_fail(mu_ctx *ctx, hipError_t e, const char *what) {
 
 mu_status DevBuf::ensure(mu_ctx *ctx, size_t bytes, bool zero) {
   if (bytes <= cap) return MU_OK;
+  if (fixed) {
+    set_err(ctx, "the launch needs %zu bytes of partial slots, more than the %zu bytes of the fixed slot array",
+            bytes, cap);
+    return MU_E_UNSUPPORTED;
+  }
   if (ptr) {
     hipStreamSynchronize(ctx->stream);
     hipFree(ptr);
@@ -68,7 +73,7 @@ mu_status DevBuf::ensure(mu_ctx *ctx, size_t bytes, bool zero) {
 }
 
 void DevBuf::release() {
-  if (ptr) hipFree(ptr);
+  if (ptr && !fixed) hipFree(ptr);
   ptr = nullptr;
   cap = 0;
 }
@@ -137,9 +142,14 @@ extern "C" mu_status mu_ctx_create(int device, void *hip_stream, unsigned flags,
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MU_E_DEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MU_E_UNSUPPORTED;
+  // the allocation-free entry point's slots on this device (looked up once
+  // per device, with the device current); without them only that entry
+  // point is unavailable
+  const hipError_t scratch_e = static_scratch_init(device);
   mu_ctx *c = new mu_ctx();
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  c->scratch = scratch_e == hipSuccess ? static_scratch(device) : nullptr;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->own_stream = false;
@@ -869,7 +879,8 @@ struct Pending {
 // w_force > 0 replaces the chosen bins per wave.
 static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_kind, const double *dp,
                              int32_t n_vec, double *dc, double *dh, double *dg, double *dm, int mode, hipStream_t s,
-                             DevBuf &partial, Pending &pend, bool launch = true, int64_t w_force = 0) {
+                             DevBuf &partial, Pending &pend, bool launch = true, int64_t w_force = 0,
+                             bool no_alloc = false) {
   mu_status st;
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
   int anchor = ctx->anchor_every;
@@ -924,6 +935,10 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   pend.shape = shape;
   pend.f64 = d->f64;
   if (!launch) return MU_OK;
+  if (no_alloc) {  // no timing events (they are created on demand)
+    hipError_t e = launch_eval(a, mode, d->f64, shape, s);
+    return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "evaluation launch");
+  }
   int ti = ctx->time_begin(mode == kModeGrad    ? MU_TIME_EVAL_GRAD
                            : mode == kModeModel ? MU_TIME_EVAL_MODEL
                                                 : MU_TIME_EVAL_COST,
@@ -1102,6 +1117,36 @@ extern "C" mu_status mu_chi2_eval(mu_ctx *ctx, const mu_data *data, const mu_the
   }
   return eval_uniform(ctx, const_cast<mu_data *>(data), th, cost_kind, params, n_vec, mem, cost, cost_per_histo,
                       nullptr, nullptr, kModeCost);
+}
+
+extern "C" mu_status mu_chi2_eval_static(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
+                                         const double *params, int32_t n_vec, double *cost, double *cost_per_histo) {
+  if (!ctx) return MU_E_ARG;
+  mu_status st = check_pair(ctx, data, th);
+  if (st != MU_OK) return st;
+  if (!cost) {
+    set_err(ctx, "cost output is NULL");
+    return MU_E_ARG;
+  }
+  if ((st = check_eval_args(ctx, cost_kind, MU_MEM_DEVICE, n_vec, params)) != MU_OK) return st;
+  if (!ctx->scratch) {
+    set_err(ctx, "the allocation-free slots of device %d were not found (hipGetSymbolAddress failed)", ctx->device);
+    return MU_E_DEVICE;
+  }
+  hipSetDevice(ctx->device);
+  // the same launch as mu_chi2_eval with device memory, its slots in the
+  // device's static array (a fixed buffer: a launch needing more slots is
+  // refused before anything is enqueued)
+  DevBuf slots;
+  slots.ptr = ctx->scratch;
+  slots.cap = (size_t)kStaticSlots * kSlot * sizeof(double);
+  slots.fixed = true;
+  Pending pend;
+  st = eval_launch(ctx, const_cast<mu_data *>(data), th, cost_kind, params, n_vec, cost, cost_per_histo, nullptr,
+                   nullptr, kModeCost, ctx->stream, slots, pend, true, 0, true);
+  if (st != MU_OK) return st;
+  hipError_t e = launch_merge(pend.a, pend.mode, pend.n_vec, ctx->stream);
+  return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "merge launch");
 }
 
 extern "C" mu_status mu_chi2_grad(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,

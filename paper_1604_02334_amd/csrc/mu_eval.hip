@@ -36,6 +36,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include <cmath>
@@ -1611,6 +1612,40 @@ hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, 
                              : launch_typed<MU_COST_CHI2, kModeCost>(a, count_f64, shape, s);
   return mode == kModeGrad ? launch_typed<MU_COST_POISSON, kModeGrad>(a, count_f64, shape, s)
                            : launch_typed<MU_COST_POISSON, kModeCost>(a, count_f64, shape, s);
+}
+
+// ------------------------------------------------------ allocation-free slots
+
+// Partial slots of the allocation-free entry point (mu_chi2_eval_static): one
+// array per device, part of the code object, held until the process ends.
+// Host code never passes the array's name to a kernel: it uses the address
+// hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) double scratch[(size_t)kStaticSlots * kSlot];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void *ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[device] = static_cast<double *>(ptr);
+  if (cur != device) hipSetDevice(cur);
+  return e;
+}
+
+double *static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
 }
 
 }  // namespace mu

@@ -152,6 +152,14 @@ struct LaunchArgs {
 };
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s);
+// Slots of the allocation-free entry point: kStaticSlots per device, in a
+// __device__ array; static_scratch_init (with the device made current)
+// looks up its address on `device` once; static_scratch returns it (null
+// before init).
+constexpr int kStaticSlots = 32768;  // 8 MiB of slots
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch_init(int device);
+double *static_scratch(int device);
 // A gradient launch g and a cost launch c of the same dataset and theory as
 // one launch, for the cases eval_grad_cost_fused accepts (chi^2, compiled
 // shapes, 32-bit counts; others take two launches); hipErrorNotSupported

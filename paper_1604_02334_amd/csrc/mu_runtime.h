@@ -20,10 +20,12 @@ constexpr int kMaxSplit = 1 << 26;  // largest explicit bins-per-unit value
 constexpr int kMaxGradSplit = 1 << 20;
 constexpr int kDefaultAnchor = 64;
 
-// Grow-only device buffer owned by a context.
+// Grow-only device buffer owned by a context.  A fixed buffer (memory the
+// buffer does not own) never grows: ensure() then refuses larger requests.
 struct DevBuf {
   void *ptr = nullptr;
   size_t cap = 0;
+  bool fixed = false;
   mu_status ensure(mu_ctx *ctx, size_t bytes, bool zero);
   void release();
 };
@@ -77,6 +79,7 @@ struct mu_ctx {
   double *d_inv = nullptr;  // [kInvTab] 1 / max(i, 1): source of the kernels' LDS table
   // partial_aux: the gradient pass's slots in mu_chi2_eval_grad
   mu::DevBuf partial, partial_aux, dparams, dout, djobs;
+  double *scratch = nullptr;  // this device's allocation-free slots (static_scratch)
   mu::HostBuf staging, staging_out;
   std::vector<mu::DevBuf> extra;
   void release_all();

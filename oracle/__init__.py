@@ -16,7 +16,9 @@ definitions:
 Modules: ``model`` (cost and analytic gradient), ``scalar`` (pure-Python
 cross-check for tiny inputs), ``fit`` (reference minimiser), ``errors``
 (Gauss-Newton Hessian, covariance, likelihood profiles and their
-one-standard-deviation crossings), ``seeder``
+one-standard-deviation crossings), ``expr`` (user-defined asymmetry
+expressions, the run-time compiled theories' language, with symbolic
+derivatives), ``seeder``
 (reference network with BF16 rounding), ``philox`` (counter-based generator
 from its published definition; the seeder's parameter draws and expected
 rebinned counts live in ``seeder``).

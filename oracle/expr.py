@@ -14,9 +14,17 @@ Grammar (whitespace ignored):
     power   := primary ("^" unary)?
     primary := number | "t" | "pi" | "p" "[" int "]" | "f" "[" int "]"
              | name "(" expr ("," expr)* ")" | "(" expr ")"
-names: exp, log, sqrt, sin, cos, pow(a, b), and the primitives se(lambda),
-ge(lambda, beta), sg(sigma), stg(sigma), tf(phi, nu) of Listing 2 / 3 (t is
-implicit in them).  p[i] is the parameter at slot i of the histogram's map
+names: exp, log, sqrt, sin, cos, pow(a, b), j0 (Bessel function of the first
+kind, order 0), the primitives se(lambda), ge(lambda, beta), sg(sigma),
+stg(sigma), tf(phi, nu) of Listing 2 / 3, and further relaxation and
+precession functions of muSR practice (the paper refers to a full list of
+predefined functions without printing it; these are the standard closed
+forms): sekt(a) = 1/3 + 2/3 (1 - a t) e^(-a t) (static Lorentzian
+Kubo-Toyabe), ab(sigma, gamma) = exp(-(sigma/gamma)^2 (e^(-gamma t) - 1 +
+gamma t)) (Abragam), b(phi, nu) = J0(2 pi nu t + phi) (Bessel precession),
+ifld(alpha, phi, nu, lT, lL) = alpha cos(2 pi nu t + phi) e^(-lT t) +
+(1 - alpha) e^(-lL t) (internal field) and ibsl(...) the same with J0 in
+place of cos.  t is implicit in every primitive.  p[i] is the parameter at slot i of the histogram's map
 row, f[i] the function value at slot i (f = F p + f0).
 """
 
@@ -26,11 +34,13 @@ import math
 import re
 
 import numpy as np
+from scipy import special
 
 from . import model
 
-FUNCS = {"exp": 1, "log": 1, "sqrt": 1, "sin": 1, "cos": 1, "pow": 2,
-         "se": 1, "ge": 2, "sg": 1, "stg": 1, "tf": 2}
+FUNCS = {"exp": 1, "log": 1, "sqrt": 1, "sin": 1, "cos": 1, "pow": 2, "j0": 1,
+         "se": 1, "ge": 2, "sg": 1, "stg": 1, "tf": 2,
+         "sekt": 1, "ab": 2, "b": 2, "ifld": 5, "ibsl": 5}
 _TOK = re.compile(r"\s*(?:(\d+\.\d*(?:[eE][+-]?\d+)?|\.\d+(?:[eE][+-]?\d+)?|\d+(?:[eE][+-]?\d+)?)|([A-Za-z_]\w*)|(.))")
 
 
@@ -181,6 +191,8 @@ def evaluate(node, t, val):
     name, args = node[1], [evaluate(a, t, val) for a in node[2]]
     if name in ("exp", "log", "sqrt", "sin", "cos"):
         return getattr(np, name)(args[0])
+    if name in ("j0", "j1"):
+        return getattr(special, name)(args[0])
     if name == "pow":
         return np.power(args[0], args[1])
     # the primitives of Listing 2 / 3, with t implicit
@@ -199,6 +211,19 @@ def _prim_array(name, t, args):
         return 1.0 / 3.0 + (2.0 / 3.0) * (1.0 - s2) * np.exp(-0.5 * s2)
     if name == "tf":
         return np.cos(2.0 * np.pi * args[1] * t + args[0])
+    if name == "sekt":
+        x = args[0] * t
+        return 1.0 / 3.0 + (2.0 / 3.0) * (1.0 - x) * np.exp(-x)
+    if name == "ab":
+        s, g = args
+        return np.exp(-(s / g) ** 2 * (np.exp(-g * t) - 1.0 + g * t))
+    if name == "b":
+        return special.j0(2.0 * np.pi * args[1] * t + args[0])
+    if name in ("ifld", "ibsl"):
+        al, phi, nu, lt, ll = args
+        x = 2.0 * np.pi * nu * t + phi
+        osc = np.cos(x) if name == "ifld" else special.j0(x)
+        return al * osc * np.exp(-lt * t) + (1.0 - al) * np.exp(-ll * t)
     raise ValueError(name)
 
 
@@ -229,6 +254,24 @@ def _expand(node):
                  ("*", ("-", ("num", 1.0), s2), ("call", "exp", [("*", ("num", -0.5), s2)]))))
     if name == "tf":
         return ("call", "cos", [("+", ("*", ("*", ("*", ("num", 2.0), ("num", math.pi)), args[1]), t), args[0])])
+    one = ("num", 1.0)
+    if name == "sekt":
+        x = ("*", args[0], t)
+        return ("+", ("/", one, ("num", 3.0)),
+                ("*", ("/", ("num", 2.0), ("num", 3.0)), ("*", ("-", one, x), ("call", "exp", [("neg", x)]))))
+    if name == "ab":
+        s, g = args
+        r = ("/", s, g)
+        gt = ("*", g, t)
+        return ("call", "exp", [("neg", ("*", ("*", r, r), ("+", ("-", ("call", "exp", [("neg", gt)]), one), gt)))])
+    phase = lambda phi, nu: ("+", ("*", ("*", ("*", ("num", 2.0), ("num", math.pi)), nu), t), phi)
+    if name == "b":
+        return ("call", "j0", [phase(args[0], args[1])])
+    if name in ("ifld", "ibsl"):
+        al, phi, nu, lt, ll = args
+        osc = ("call", "cos" if name == "ifld" else "j0", [phase(phi, nu)])
+        return ("+", ("*", ("*", al, osc), ("call", "exp", [("neg", ("*", lt, t))])),
+                ("*", ("-", one, al), ("call", "exp", [("neg", ("*", ll, t))])))
     return ("call", name, args)
 
 
@@ -268,6 +311,8 @@ def derivative(node, var):
         return ("*", ("call", "cos", [u]), du)
     if name == "cos":
         return ("neg", ("*", ("call", "sin", [u]), du))
+    if name == "j0":
+        return ("neg", ("*", ("call", "j1", [u]), du))
     if name == "pow":
         return derivative(("pow", args[0], args[1]), var)
     raise ValueError(name)
@@ -293,6 +338,8 @@ def _eval_safe(node, t, val):
         with np.errstate(divide="ignore", invalid="ignore"):
             if node[1] == "pow":
                 return np.power(args[0], args[1])
+            if node[1] in ("j0", "j1"):
+                return getattr(special, node[1])(args[0])
             return getattr(np, node[1])(args[0])
     return evaluate(node, t, val)
 

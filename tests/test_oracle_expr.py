@@ -86,3 +86,58 @@ def test_symbolic_gradient_against_finite_differences():
 def test_syntax_errors(bad):
     with pytest.raises(ValueError):
         expr.parse(bad)
+
+
+def test_further_primitives_closed_forms():
+    """sekt: 1 at t = 0, the 1/3 tail, its minimum 1/3 - (2/3) e^-2 at a t = 2;
+    ab: the Gaussian exp(-(sigma t)^2 / 2) as gamma -> 0 and the motional
+    narrowing exp(-sigma^2 t / gamma) as gamma -> infinity; b: J0's first zero
+    and b(phi, 0) = J0(phi); ifld / ibsl: alpha = 1 and alpha = 0 reduce to
+    the single terms."""
+    t = np.array([0.0, 2.0, 1e3])
+    ev = lambda e, v=None: expr.evaluate(expr.parse(e), t, v or {})
+    np.testing.assert_allclose(ev("sekt(1.0)"), [1.0, 1.0 / 3.0 - (2.0 / 3.0) * np.exp(-2.0), 1.0 / 3.0],
+                               rtol=1e-15)
+    d = expr._expand(expr.parse("sekt(p[0])"))
+    dd = expr._eval_safe(expr.derivative(d, ("p", 0)), np.array([2.0]), {("p", 0): 1.0})
+    assert abs(dd[0]) < 1e-15  # stationary at a t = 2
+    tt = np.linspace(0, 3, 31)
+    # small gamma: the exponent's series sigma^2 (t^2/2 - g t^3/6 + g^2 t^4/24 - g^3 t^5/120 + ...),
+    # whose leading term is the Gaussian
+    g = 1e-2
+    a = expr.evaluate(expr.parse(f"ab(0.7, {g})"), tt, {})
+    ser = 0.49 * (tt ** 2 / 2 - g * tt ** 3 / 6 + g ** 2 * tt ** 4 / 24 - g ** 3 * tt ** 5 / 120)
+    np.testing.assert_allclose(a, np.exp(-ser), rtol=1e-8)
+    # large gamma (gamma t >= 1e3 here, e^(-gamma t) negligible): exp(-sigma^2 t / gamma + sigma^2 / gamma^2)
+    a = expr.evaluate(expr.parse("ab(0.7, 1e4)"), tt[1:], {})
+    np.testing.assert_allclose(a, np.exp(-0.49 * tt[1:] / 1e4 + 0.49 / 1e8), rtol=1e-12)
+    z = 2.404825557695773
+    assert abs(expr.evaluate(expr.parse(f"b({z}, 0)"), np.array([1.0]), {})[0]) < 1e-15
+    assert abs(expr.evaluate(expr.parse("b(0.5, 0)"), np.array([1.0]), {})[0] - 0.938469807240813) < 1e-14
+    f1 = expr.evaluate(expr.parse("ifld(1, 0.3, 1.2, 0.4, 2.0)"), tt, {})
+    np.testing.assert_allclose(f1, np.cos(2 * np.pi * 1.2 * tt + 0.3) * np.exp(-0.4 * tt), rtol=1e-14)
+    f0 = expr.evaluate(expr.parse("ibsl(0, 0.3, 1.2, 0.4, 2.0)"), tt, {})
+    np.testing.assert_allclose(f0, np.exp(-2.0 * tt), rtol=1e-14)
+
+
+def test_further_primitives_gradient_against_finite_differences():
+    e = "p[2]*sekt(p[3]) + p[4]*ab(p[5], p[6]) + 0.1*b(p[7], p[8]) + 0.05*ifld(p[9], p[7], p[8], p[3], p[6])" \
+        " - 0.02*ibsl(p[9], p[7], p[8], p[5], p[3])"
+    n = 10
+    ex = expr.theory_desc(e, TAU, ("p", 0), ("p", 1), [list(range(n))], n)
+    p = np.array([900.0, 3.0, 0.15, 0.6, 0.1, 0.5, 1.5, 0.3, 0.8, 0.6])
+    h = [_h(800, 0.01)]
+    c = [np.random.default_rng(6).poisson(expr.model_expr_full(ex, h[0], p)).astype(float)]
+    q = p * (1.0 + 0.02 * np.sin(np.arange(n)))
+    g = expr.grad_expr(ex, h, c, q)
+    for k in range(n):
+        hk = 1e-4 * max(abs(q[k]), 1e-2)
+
+        def cd(s):
+            a, b = q.copy(), q.copy()
+            a[k] += s
+            b[k] -= s
+            return (expr.cost_expr(ex, h, c, a) - expr.cost_expr(ex, h, c, b)) / (2 * s)
+
+        fd = (4 * cd(hk / 2) - cd(hk)) / 3
+        assert abs(g[k] - fd) <= 1e-7 * abs(fd) + 1e-9 * np.max(np.abs(g)), (k, g[k], fd)

@@ -170,6 +170,63 @@ mu_status mu_theory_create(mu_ctx *ctx, const mu_theory_desc *d, mu_theory **out
 mu_status mu_theory_destroy(mu_theory *th);
 int32_t mu_theory_npar(const mu_theory *th);
 
+/* ------------------------------------------------- run-time compiled theory */
+
+/* A theory whose asymmetry A(t) is written as an expression and compiled at
+ * run time (the paper's user functions, Sec. 4.2.1 and Listing 3, there a C
+ * function compiled when the fit starts; here hipRTC for gfx950).  The model
+ * stays N = N0 e^(-t/tau_mu) (1 + A(t)) + Nbkg (Eq. 1) with N0 and Nbkg
+ * references as for theory programs.  Grammar (whitespace ignored):
+ *   expr    := term (("+" | "-") term)*
+ *   term    := unary (("*" | "/") unary)*
+ *   unary   := ("-" | "+") unary | power
+ *   power   := primary ("^" unary)?
+ *   primary := number | "t" | "pi" | "p[" slot "]" | "f[" slot "]"
+ *            | name "(" expr ("," expr)* ")" | "(" expr ")"
+ * p[i] is the parameter at slot i of the histogram's map row, f[i] the
+ * function value at slot i (f = F p + f0); names: exp, log, sqrt, sin, cos,
+ * pow(a, b), j0 (Bessel J0), the primitives se(lambda), ge(lambda, beta),
+ * sg(sigma), stg(sigma), tf(phi, nu) (as MU_SE .. MU_TF), and
+ *   sekt(a)        1/3 + 2/3 (1 - a t) e^(-a t)   (static Lorentzian Kubo-Toyabe)
+ *   ab(sigma, g)   exp(-(sigma/g)^2 (e^(-g t) - 1 + g t))   (Abragam)
+ *   b(phi, nu)     J0(2 pi nu t + phi)   (Bessel precession)
+ *   ifld(alpha, phi, nu, lT, lL)   alpha cos(2 pi nu t + phi) e^(-lT t) + (1 - alpha) e^(-lL t)
+ *   ibsl(alpha, phi, nu, lT, lL)   the same with J0 in place of cos
+ * with t implicit in every primitive.  At most
+ * 28 distinct references.  Each bin is evaluated directly (no recurrences),
+ * with the derivatives in the references carried as dual numbers, so costs,
+ * gradients, model values, batched launches, fits and mu_hesse all accept
+ * such a theory (the allocation-free entry point too, since compilation
+ * happens at creation).  Division by zero, log of a non-positive value and
+ * the like give non-finite costs, as non-finite parameters do. */
+typedef struct {
+  double tau_mu;           /* muon lifetime in us, > 0 */
+  mu_ref n0, nbkg;         /* N0^j and Nbkg^j */
+  const char *asymmetry;   /* A(t), the grammar above */
+  const int32_t *map;      /* [n_rows][n_slots] */
+  int32_t n_rows, n_slots;
+  const double *F;         /* [n_fun][n_par] or NULL when n_fun == 0 */
+  const double *f0;        /* [n_fun] or NULL when n_fun == 0 */
+  int32_t n_fun;
+  int32_t n_par;           /* 1 .. MU_MAX_PAR */
+} mu_expr_theory_desc;
+
+/* Parse and validate without a device (the map rules of mu_theory_check for
+ * N0, Nbkg and every reference of the expression).  MU_E_ARG for a syntax
+ * error (the message gives the offset), an unknown name, a wrong argument
+ * count or a bad reference; MU_E_UNSUPPORTED for more than 28 references. */
+mu_status mu_theory_check_expr(const mu_expr_theory_desc *d, char *msg, int32_t msg_len);
+/* The HIP source that would be compiled (*needed: its size with the final
+ * zero; buf may be NULL). */
+mu_status mu_theory_expr_source(const mu_expr_theory_desc *d, char *buf, int64_t buf_len, int64_t *needed);
+/* Compile with hipRTC for gfx950 without a device (no context): MU_E_ARG
+ * with the compiler's log in msg if the generated source does not build. */
+mu_status mu_theory_compile_check(const mu_expr_theory_desc *d, char *msg, int32_t msg_len);
+/* Create the theory: parse, compile (once per context and distinct source;
+ * the module is kept until mu_ctx_destroy) and upload.  Destroy with
+ * mu_theory_destroy. */
+mu_status mu_theory_create_expr(mu_ctx *ctx, const mu_expr_theory_desc *d, mu_theory **out);
+
 /* -------------------------------------------------------------- evaluation */
 
 /* Cost of n_vec parameter vectors (params: [n_vec][n_par] row-major) over
@@ -395,6 +452,52 @@ mu_status mu_fit_batch(mu_ctx *ctx, int32_t n_fits, const mu_data *const *data, 
                        mu_cost cost_kind, int32_t ld, const double *start, const mu_fit_opts *opts,
                        double *params_out, double *cov_out, mu_fit_result *res);
 
+/* ------------------------------------------------------- parameter errors */
+
+/* After the minimum (Sec. 4 fits with Minuit2's minimisation; the steps that
+ * usually follow are its HESSE and MINOS): both costs are -2 ln L up to a
+ * constant (Eqs. 2-3), so the covariance is 2 H^-1 and a rise of `up` = 1 in
+ * the profiled cost marks one standard deviation. */
+typedef enum {
+  MU_HESSE_GAUSS_NEWTON = 0, /* H = sum_n c_n (dN_n/dp)(dN_n/dp)^T with c_n = d^2 term / dN^2 (2/v for chi^2,
+                                2 d / N^2 for the likelihood): the bins' Jacobian rows from the evaluation kernel,
+                                their Gram matrix per histogram on the FP64 matrix cores, the chain rule through
+                                the map and function array on the host */
+  MU_HESSE_DIFF = 1          /* central differences of the analytic gradient, the 2n points in one launch
+                                (step 1e-5 max(|p_k|, 1e-3)) */
+} mu_hesse_method;
+
+/* Hessian of the cost at params (host, [n_par]) of one dataset and theory:
+ * hess [n_par][n_par] (host; zero rows and columns for parameters with
+ * fixed[k] != 0; fixed may be NULL).  cov [n_par][n_par] (host, may be NULL):
+ * 2 H^-1 over the free block (zero rows / columns for fixed parameters), or
+ * all NaN when the free block is not positive definite; *pos_def (may be
+ * NULL) says which.  MU_E_ARG for a non-finite parameter or an unknown method
+ * or cost kind.  Synchronous. */
+mu_status mu_hesse(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind, int32_t method,
+                   const double *params, const uint8_t *fixed, double *hess, double *cov, int32_t *pos_def);
+
+/* Likelihood profile of parameter k: at each of the n_points values, the cost
+ * minimised over every other parameter not fixed (all points as one batched
+ * fit, mu_fit_batch with analytic gradients and polish, started at p_min
+ * moved along k's correlations).  prof_cost [n_points]; prof_params
+ * [n_points][n_par] and status [n_points] (the fits' status) may be NULL.
+ * Host memory; synchronous. */
+mu_status mu_profile(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind, const double *p_min,
+                     const uint8_t *fixed, int32_t k, int32_t n_points, const double *values, double *prof_cost,
+                     double *prof_params, int32_t *status);
+
+/* MINOS-like errors of parameter k around the minimum p_min: the offsets
+ * err_lo < 0 < err_hi where the profile of k reaches cost(p_min) + up.  Both
+ * sides start one Hessian standard deviation out (doubled until bracketed)
+ * and are refined together, one two-point mu_profile per round, by
+ * interpolation in the squared offset (exact for a parabolic profile) until
+ * the profile is within 1e-9 up of the target.  *n_rounds (may be NULL): the
+ * rounds used.  MU_E_STATE (nothing written) if a side has not converged in 60
+ * rounds.  Host memory; synchronous. */
+mu_status mu_minos(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind, const double *p_min,
+                   const uint8_t *fixed, int32_t k, double up, double *err_lo, double *err_hi, int32_t *n_rounds);
+
 /* ------------------------------------------------------------------ seeder */
 
 /* A learned seeder proposes start parameters for fits of the exp*cos family
@@ -454,6 +557,16 @@ mu_status mu_seeder_forward(mu_ctx *ctx, mu_seeder *s, const uint16_t *x_bf16, i
  * Adam update (b1 0.9, b2 0.999, eps 1e-8) when update != 0.  loss may be NULL. */
 mu_status mu_seeder_train_step(mu_ctx *ctx, mu_seeder *s, const uint16_t *x_bf16, const float *targets, int32_t B,
                                float lr, int32_t update, unsigned mem, float *loss);
+/* The buffers of one layer (0 .. 3) as the last forward pass (mu_seeder_forward,
+ * mu_seeder_train_step, mu_seed_infer) left them, for the first B samples of
+ * that pass (host memory, any output may be NULL): x_in [B][K_l] the layer's
+ * BF16 input (bit patterns; layer 0: the network input, else the BF16 ReLU of
+ * the previous layer's pre-activation), z [B][N_l] its FP32 pre-activation
+ * (layer 3: the output), and after a training step dz [B][N_l] the FP32
+ * gradient of the loss in z and g [B][N_l] its BF16 copy used by the GEMMs.
+ * MU_E_STATE when B exceeds the samples of the last pass. */
+mu_status mu_seeder_layer(mu_ctx *ctx, const mu_seeder *s, int32_t layer, int32_t B, uint16_t *x_in, float *z,
+                          float *dz, uint16_t *g);
 /* Train on freshly generated samples; loss_curve [steps] (host) may be NULL. */
 mu_status mu_seeder_train(mu_ctx *ctx, mu_seeder *s, const mu_seed_train_opts *opts, float *loss_curve);
 /* Start vectors (N0, Nbkg, A, lambda, nu, phi) for n datasets, each one

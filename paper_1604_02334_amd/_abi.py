@@ -18,6 +18,7 @@ MU_COST_CHI2, MU_COST_POISSON = 0, 1
 MU_MEM_HOST, MU_MEM_DEVICE = 0, 1
 MU_SE, MU_GE, MU_SG, MU_STG, MU_TF = range(5)
 MU_REF_PAR, MU_REF_FUN, MU_REF_LIT = range(3)
+MU_HESSE_GAUSS_NEWTON, MU_HESSE_DIFF = 0, 1
 MU_MAX_TERMS = 4
 MU_MAX_FACTORS_PER_TERM = 3
 MU_MAX_PAR = 1024
@@ -56,6 +57,12 @@ class mu_theory_desc(C.Structure):
     _fields_ = [("tau_mu", C.c_double), ("n0", mu_ref), ("nbkg", mu_ref),
                 ("terms", C.POINTER(mu_term)), ("n_terms", C.c_int32),
                 ("factors", C.POINTER(mu_factor)), ("n_factors", C.c_int32),
+                ("map", C.POINTER(C.c_int32)), ("n_rows", C.c_int32), ("n_slots", C.c_int32),
+                ("F", dp), ("f0", dp), ("n_fun", C.c_int32), ("n_par", C.c_int32)]
+
+
+class mu_expr_theory_desc(C.Structure):
+    _fields_ = [("tau_mu", C.c_double), ("n0", mu_ref), ("nbkg", mu_ref), ("asymmetry", C.c_char_p),
                 ("map", C.POINTER(C.c_int32)), ("n_rows", C.c_int32), ("n_slots", C.c_int32),
                 ("F", dp), ("f0", dp), ("n_fun", C.c_int32), ("n_par", C.c_int32)]
 
@@ -120,12 +127,21 @@ def lib():
         "mu_theory_create": (S, [vp, C.POINTER(mu_theory_desc), C.POINTER(vp)]),
         "mu_theory_destroy": (S, [vp]),
         "mu_theory_npar": (C.c_int32, [vp]),
+        "mu_theory_check_expr": (S, [C.POINTER(mu_expr_theory_desc), C.c_char_p, C.c_int32]),
+        "mu_theory_expr_source": (S, [C.POINTER(mu_expr_theory_desc), C.c_char_p, C.c_int64,
+                                      C.POINTER(C.c_int64)]),
+        "mu_theory_compile_check": (S, [C.POINTER(mu_expr_theory_desc), C.c_char_p, C.c_int32]),
+        "mu_theory_create_expr": (S, [vp, C.POINTER(mu_expr_theory_desc), C.POINTER(vp)]),
         "mu_chi2_eval": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, vp, vp]),
         "mu_chi2_grad": (S, [vp, vp, vp, S, vp, C.c_int32, C.c_uint, vp, vp]),
         "mu_chi2_eval_static": (S, [vp, vp, vp, S, vp, C.c_int32, vp, vp]),
         "mu_chi2_eval_grad": (S, [vp, vp, vp, S, vp, C.c_int32, vp, C.c_int32, C.c_uint, vp, vp, vp]),
         "mu_chi2_batch": (S, [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), S, C.c_int32, vp, C.c_uint, vp, vp]),
         "mu_model_eval": (S, [vp, vp, vp, vp, C.c_uint, vp]),
+        "mu_hesse": (S, [vp, vp, vp, S, C.c_int32, vp, vp, vp, vp, C.POINTER(C.c_int32)]),
+        "mu_profile": (S, [vp, vp, vp, S, vp, vp, C.c_int32, C.c_int32, vp, vp, vp, vp]),
+        "mu_minos": (S, [vp, vp, vp, S, vp, vp, C.c_int32, C.c_double, C.POINTER(C.c_double),
+                         C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "mu_fit_batch": (S, [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), S, C.c_int32, vp,
                              C.POINTER(mu_fit_opts), vp, vp, C.POINTER(mu_fit_result)]),
     }
@@ -145,10 +161,13 @@ def exported_symbols():
                    "mu_autotune_batch", "mu_autotune_save", "mu_autotune_load", "mu_autotune_check_file",
                    "mu_histo_check", "mu_data_create",
                    "mu_data_destroy", "mu_data_bins", "mu_data_histos", "mu_data_is_f64", "mu_theory_check",
-                   "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_chi2_eval", "mu_chi2_grad",
+                   "mu_theory_create", "mu_theory_destroy", "mu_theory_npar", "mu_theory_check_expr",
+                   "mu_theory_expr_source", "mu_theory_compile_check", "mu_theory_create_expr",
+                   "mu_chi2_eval", "mu_chi2_grad",
                    "mu_chi2_eval_static",
-                   "mu_chi2_eval_grad", "mu_chi2_batch", "mu_model_eval", "mu_fit_batch",
+                   "mu_chi2_eval_grad", "mu_chi2_batch", "mu_model_eval", "mu_fit_batch", "mu_hesse", "mu_profile",
+                   "mu_minos",
                    "mu_seeder_param_count", "mu_seeder_create", "mu_seeder_destroy", "mu_seeder_get_params",
                    "mu_seeder_get_grads", "mu_seeder_steps", "mu_gen_histos", "mu_seeder_forward",
-                   "mu_seeder_train_step", "mu_seeder_train", "mu_seed_infer", "mu_seeder_save",
+                   "mu_seeder_train_step", "mu_seeder_train", "mu_seed_infer", "mu_seeder_save", "mu_seeder_layer",
                    "mu_seeder_load"])

@@ -207,11 +207,76 @@ def histo_check(histos, counts):
     return st, buf.value.decode()
 
 
+def expr_theory_desc(theory):
+    """mu_expr_theory_desc (and its arrays) from a dict with "expr" (the
+    asymmetry expression), "tau_mu", "n0", "nbkg", "map", "n_par" and
+    optionally "F", "f0"."""
+    m = np.ascontiguousarray(np.asarray(theory["map"], dtype=np.int32))
+    if m.ndim != 2:
+        raise ValueError("map must be two-dimensional")
+    text = theory["expr"].encode()
+    keep = [m, text]
+    d = A.mu_expr_theory_desc()
+    d.tau_mu = float(theory["tau_mu"])
+    d.n0 = _ref(theory["n0"])
+    d.nbkg = _ref(theory["nbkg"])
+    d.asymmetry = text
+    d.map = m.ctypes.data_as(C.POINTER(C.c_int32))
+    d.n_rows, d.n_slots = m.shape
+    F = theory.get("F")
+    if F is not None:
+        Fa = np.ascontiguousarray(np.asarray(F, dtype=np.float64))
+        f0 = np.ascontiguousarray(np.asarray(theory["f0"], dtype=np.float64))
+        keep += [Fa, f0]
+        d.F = Fa.ctypes.data_as(A.dp)
+        d.f0 = f0.ctypes.data_as(A.dp)
+        d.n_fun = Fa.shape[0]
+    else:
+        d.F = None
+        d.f0 = None
+        d.n_fun = 0
+    d.n_par = int(theory["n_par"])
+    return d, keep
+
+
+def theory_check_expr(theory):
+    """Parse and validate an expression theory without a device: (status, message)."""
+    d, keep = expr_theory_desc(theory)
+    buf = C.create_string_buffer(1024)
+    st = A.lib().mu_theory_check_expr(C.byref(d), buf, len(buf))
+    return st, buf.value.decode()
+
+
+def theory_compile_check(theory):
+    """Compile an expression theory with hipRTC without a device: (status, message or log)."""
+    d, keep = expr_theory_desc(theory)
+    buf = C.create_string_buffer(16384)
+    st = A.lib().mu_theory_compile_check(C.byref(d), buf, len(buf))
+    return st, buf.value.decode(errors="replace")
+
+
+def theory_expr_source(theory):
+    """The generated HIP source of an expression theory."""
+    d, keep = expr_theory_desc(theory)
+    need = C.c_int64()
+    _check(A.lib().mu_theory_expr_source(C.byref(d), None, 0, C.byref(need)), None, "mu_theory_expr_source")
+    buf = C.create_string_buffer(need.value)
+    _check(A.lib().mu_theory_expr_source(C.byref(d), buf, need.value, None), None, "mu_theory_expr_source")
+    return buf.value.decode()
+
+
 class Theory:
+    """A theory on the device: a program dict (terms of primitives) or, with an
+    "expr" key, a run-time compiled expression theory."""
+
     def __init__(self, ctx, theory):
-        d, keep = theory_desc(theory)
         h = C.c_void_p()
-        _check(A.lib().mu_theory_create(ctx.h, C.byref(d), C.byref(h)), ctx.h, "mu_theory_create")
+        if "expr" in theory:
+            d, keep = expr_theory_desc(theory)
+            _check(A.lib().mu_theory_create_expr(ctx.h, C.byref(d), C.byref(h)), ctx.h, "mu_theory_create_expr")
+        else:
+            d, keep = theory_desc(theory)
+            _check(A.lib().mu_theory_create(ctx.h, C.byref(d), C.byref(h)), ctx.h, "mu_theory_create")
         self.h = h
         self.addr = h.value  # the handle as an integer (batched calls pass arrays of them)
         self.ctx = ctx
@@ -532,3 +597,57 @@ def fit_batch(ctx, datas, theories, start, cost="chi2", fixed=None, analytic_gra
     rs = [{"cost": r.cost, "edm": r.edm, "n_iter": r.n_iter, "n_fcn": r.n_fcn, "n_grad": r.n_grad,
            "status": r.status} for r in res]
     return out, cov, rs
+
+
+def _fixed_array(fixed, n):
+    if fixed is None:
+        return None
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(fixed, dtype=np.uint8), (n,)))
+
+
+def hesse(ctx, data, theory, params, cost="chi2", method="gauss_newton", fixed=None):
+    """Hessian and covariance 2 H^-1 at params (host arrays).  method:
+    "gauss_newton" (Jacobian rows + FP64 matrix-core Gram kernel) or "diff"
+    (central differences of the analytic gradient).  Returns (H, cov or None
+    when H is not positive definite)."""
+    n = theory.n_par
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    if p.size != n:
+        raise ValueError("params must have n_par entries")
+    fx = _fixed_array(fixed, n)
+    H = np.empty((n, n))
+    cov = np.empty((n, n))
+    pd = C.c_int32()
+    m = {"gauss_newton": A.MU_HESSE_GAUSS_NEWTON, "diff": A.MU_HESSE_DIFF}[method]
+    _check(A.lib().mu_hesse(ctx.h, data.h, theory.h, _cost_code(cost), m, p.ctypes.data,
+                            fx.ctypes.data if fx is not None else None, H.ctypes.data, cov.ctypes.data,
+                            C.byref(pd)), ctx.h, "mu_hesse")
+    return H, (cov if pd.value else None)
+
+
+def profile(ctx, data, theory, p_min, k, values, cost="chi2", fixed=None):
+    """Profile cost of parameter k at each value (the other free parameters
+    minimised in one batched fit).  Returns (costs, params, statuses)."""
+    n = theory.n_par
+    p = np.ascontiguousarray(np.asarray(p_min, dtype=np.float64).reshape(-1))
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(-1))
+    fx = _fixed_array(fixed, n)
+    pc = np.empty(v.size)
+    pp = np.empty((v.size, n))
+    stt = np.empty(v.size, dtype=np.int32)
+    _check(A.lib().mu_profile(ctx.h, data.h, theory.h, _cost_code(cost), p.ctypes.data,
+                              fx.ctypes.data if fx is not None else None, int(k), v.size, v.ctypes.data,
+                              pc.ctypes.data, pp.ctypes.data, stt.ctypes.data), ctx.h, "mu_profile")
+    return pc, pp, stt
+
+
+def minos(ctx, data, theory, p_min, k, cost="chi2", up=1.0, fixed=None):
+    """Profile-likelihood errors of parameter k: (err_lo, err_hi, rounds)."""
+    n = theory.n_par
+    p = np.ascontiguousarray(np.asarray(p_min, dtype=np.float64).reshape(-1))
+    fx = _fixed_array(fixed, n)
+    lo, hi, r = C.c_double(), C.c_double(), C.c_int32()
+    _check(A.lib().mu_minos(ctx.h, data.h, theory.h, _cost_code(cost), p.ctypes.data,
+                            fx.ctypes.data if fx is not None else None, int(k), float(up), C.byref(lo), C.byref(hi),
+                            C.byref(r)), ctx.h, "mu_minos")
+    return lo.value, hi.value, r.value

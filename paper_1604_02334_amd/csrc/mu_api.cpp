@@ -196,6 +196,8 @@ extern "C" mu_status mu_ctx_destroy(mu_ctx *ctx) {
   if (ctx->d_inv) hipFree(ctx->d_inv);
   if (ctx->staging_free) hipEventDestroy(ctx->staging_free);
   for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
+  for (auto &m : ctx->rtc)
+    if (m.mod) hipModuleUnload(m.mod);
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   delete ctx;
   return MU_OK;
@@ -207,6 +209,8 @@ void mu_ctx::release_all() {
   dparams.release();
   dout.release();
   djobs.release();
+  jac.release();
+  gram.release();
   staging.release();
   staging_out.release();
   for (auto &b : extra) b.release();
@@ -518,8 +522,10 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
   }
   d->total = total;
   const size_t esz = d->f64 ? sizeof(double) : sizeof(uint32_t);
-  // kPrefetch lane steps (of 256 values) of zero padding: kernels read each
-  // lane's counts that many steps ahead, and reads past the last bin land here
+  // kPrefetch x kBlock values (16 lane steps of 64 values) of zero padding:
+  // kernels read each lane's counts up to kPrefetchStream (<= 16) lane steps
+  // ahead, and reads past the last bin land here
+  static_assert(kPrefetchStream * kWave <= kPrefetch * kBlock, "padding covers the deepest count prefetch");
   const size_t padded = ((size_t)total + (size_t)kPrefetch * kBlock) * esz;
   hipError_t e = hipMalloc(&d->counts, padded);
   if (e != hipSuccess) {
@@ -873,7 +879,15 @@ static mu_status check_eval_args(mu_ctx *ctx, int cost_kind, unsigned mem, int32
 struct Pending {
   LaunchArgs a;
   int mode = 0, n_vec = 0, shape = 0, f64 = 0;
+  hipFunction_t rtc = nullptr;  // run-time compiled theory's kernel
 };
+
+// The evaluation launch of a prepared uniform launch: the theory's compiled
+// shape or interpreted kernel, or its run-time compiled kernel.
+static hipError_t launch_pending(const Pending &p, int mode, hipStream_t s) {
+  if (p.rtc) return launch_rtc(p.rtc, p.a, mode, p.f64, s);
+  return launch_eval(p.a, mode, p.f64, p.shape, s);
+}
 
 // Prepares (and, unless launch is false, enqueues) one evaluation launch;
 // w_force > 0 replaces the chosen bins per wave.
@@ -934,16 +948,17 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   pend.n_vec = n_vec;
   pend.shape = shape;
   pend.f64 = d->f64;
+  pend.rtc = th->rtc_fn;
   if (!launch) return MU_OK;
   if (no_alloc) {  // no timing events (they are created on demand)
-    hipError_t e = launch_eval(a, mode, d->f64, shape, s);
+    hipError_t e = launch_pending(pend, mode, s);
     return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "evaluation launch");
   }
   int ti = ctx->time_begin(mode == kModeGrad    ? MU_TIME_EVAL_GRAD
                            : mode == kModeModel ? MU_TIME_EVAL_MODEL
                                                 : MU_TIME_EVAL_COST,
                            s);
-  hipError_t e = launch_eval(a, mode, d->f64, shape, s);
+  hipError_t e = launch_pending(pend, mode, s);
   ctx->time_end(ti, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
   return MU_OK;
@@ -1059,7 +1074,7 @@ mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int 
   // least half a cost range, but at least 64 gradient waves (C2: 8192 bins
   // per wave in place of the 1024-2048 a gradient launch of its own prefers).
   const int shape = ctx->specialize ? th->shape : kShapeGeneric;
-  const bool fused = eval_grad_cost_fused(d->f64, shape, cost_kind);
+  const bool fused = !th->rtc_fn && eval_grad_cost_fused(d->f64, shape, cost_kind);
   int64_t wg = 0;
   if (fused && ctx->tile_bins == 0) {
     int anchor_g = 0;
@@ -1076,11 +1091,11 @@ mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int 
     ctx->time_end(ti, ctx->stream);
   } else {
     int ti = ctx->time_begin(MU_TIME_EVAL_GRAD, ctx->stream);
-    e = launch_eval(pg_.a, kModeGrad, pg_.f64, pg_.shape, ctx->stream);
+    e = launch_pending(pg_, kModeGrad, ctx->stream);
     ctx->time_end(ti, ctx->stream);
     if (e == hipSuccess) {
       ti = ctx->time_begin(MU_TIME_EVAL_COST, ctx->stream);
-      e = launch_eval(pc_.a, kModeCost, pc_.f64, pc_.shape, ctx->stream);
+      e = launch_pending(pc_, kModeCost, ctx->stream);
       ctx->time_end(ti, ctx->stream);
     }
   }
@@ -1233,20 +1248,40 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
   const int mode = grad ? kModeGrad : kModeCost;
   const int f64 = data[0]->f64;
   // launch 0: jobs of compiled shapes (each segment runs its job's shape);
-  // launch 1: the others (interpreted theory programs, or FP64 counts)
+  // launch 1: the interpreted theory programs (or FP64 counts); then one
+  // launch per run-time compiled theory kernel
   std::vector<int32_t> list;
   list.reserve(n_jobs);
   struct Group {
     int32_t first = 0, n = 0;  // in `list`
     int64_t total = 0, W = 0, n_units = 0;
     int32_t n_histo = 0, slot_base = 0, anchor = 0, in_table = 1;
-  } grp[2];
-  for (int g = 0; g < 2; ++g) {
+    hipFunction_t rtc = nullptr;
+  };
+  std::vector<Group> grp(2);
+  for (int j = 0; j < n_jobs; ++j)
+    if (th[j]->rtc_fn) {
+      bool seen = false;
+      for (size_t g = 2; g < grp.size(); ++g) seen = seen || grp[g].rtc == th[j]->rtc_fn;
+      if (!seen) {
+        grp.emplace_back();
+        grp.back().rtc = th[j]->rtc_fn;
+      }
+    }
+  const int n_groups = (int)grp.size();
+  for (int g = 0; g < n_groups; ++g) {
     Group &G = grp[g];
     G.first = (int32_t)list.size();
     for (int j = 0; j < n_jobs; ++j) {
-      const bool fixed = ctx->specialize && !f64 && th[j]->shape != kShapeGeneric;
-      if (fixed != (g == 0)) continue;
+      int jg;
+      if (th[j]->rtc_fn) {
+        jg = -1;
+        for (int q = 2; q < n_groups; ++q)
+          if (grp[q].rtc == th[j]->rtc_fn) jg = q;
+      } else {
+        jg = (ctx->specialize && !f64 && th[j]->shape != kShapeGeneric) ? 0 : 1;
+      }
+      if (jg != g) continue;
       list.push_back(j);
       G.total += data[j]->total;
       G.n_histo += data[j]->n_histo;
@@ -1255,11 +1290,11 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     G.n = (int32_t)list.size() - G.first;
   }
   int64_t slots = 0, units_all = 0;
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < n_groups; ++g) {
     Group &G = grp[g];
     if (G.n == 0) continue;
     int anchor = ctx->anchor_every;
-    G.W = ctx->pick_batch(g == 1, mode, cost_kind, f64, G.total, &anchor);
+    G.W = ctx->pick_batch(g != 0, mode, cost_kind, f64, G.total, &anchor);
     if (mode == kModeGrad) G.W = std::min<int64_t>(G.W, kMaxGradSplit);
     G.anchor = anchor;
     G.n_units = (G.total + G.W - 1) / G.W;
@@ -1309,8 +1344,8 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
   }
   std::memcpy(hl, list.data(), list_bytes);
   int64_t start_at = 0;  // first unit_start entry of the group
-  int64_t start_of[2] = {0, 0};
-  for (int g = 0; g < 2; ++g) {
+  std::vector<int64_t> start_of(n_groups, 0);
+  for (int g = 0; g < n_groups; ++g) {
     const Group &G = grp[g];
     start_of[g] = start_at;
     if (G.n == 0) continue;
@@ -1332,7 +1367,7 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
       J.jbase = jbase;
       J.slot_base = G.slot_base;
       J.n_histo = data[j]->n_histo;
-      J.shape = g == 0 ? th[j]->shape : kShapeGeneric;
+      J.shape = g == 0 ? th[j]->shape : kShapeGeneric;  // (run-time compiled groups do not read it)
       goff += data[j]->total;
       jbase += data[j]->n_histo;
     }
@@ -1361,7 +1396,7 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(jobs)");
   ctx->mark_staging();
   double *part = static_cast<double *>(ctx->partial.ptr);
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < n_groups; ++g) {
     const Group &G = grp[g];
     if (G.n == 0) continue;
     LaunchArgs a;
@@ -1379,7 +1414,7 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     a.counts_in_table = G.in_table;
     a.partial = part + (size_t)G.slot_base * kSlot;
     const int ti = ctx->time_begin(grad ? MU_TIME_EVAL_GRAD : MU_TIME_EVAL_COST, ctx->stream);
-    e = launch_eval_batch(a, mode, f64, g == 1, ctx->stream);
+    e = G.rtc ? launch_rtc(G.rtc, a, mode, f64, ctx->stream) : launch_eval_batch(a, mode, f64, g == 1, ctx->stream);
     ctx->time_end(ti, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched evaluation launch");
   }

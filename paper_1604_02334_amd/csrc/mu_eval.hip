@@ -710,7 +710,7 @@ struct SegIn {
 };
 
 // One segment (see SegIn).
-template <int COST, int MODE, typename CT, typename Sh, int TAB>
+template <int COST, int MODE, typename CT, typename Sh, int TAB, int PF = kPrefetch>
 __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   const int tid = threadIdx.x;
   const DevTheory *th = S.th;
@@ -835,7 +835,8 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   // step constants), and E = N0 (1 + sum of w_k / 3 over lone-stg terms)
   // e^(-t/tau) carries the constant part of lone stg terms. stg factors keep
   // (2/3) g in their Gaussian state and u = sigma t as a state of their own.
-  constexpr bool kScaled = MODE != kModeGrad && Sh::kScalable;
+  constexpr bool kDeriv = MODE == kModeGrad || MODE == kModeJac;  // per-factor values and derivatives
+  constexpr bool kScaled = !kDeriv && Sh::kScalable;
   double ecoef = n0;  // E = ecoef e^(-t/tau)
   double su[kSlots];  // sigma h for stg slots
   if constexpr (kScaled) {
@@ -926,22 +927,22 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   const int n_max = n_full + ((seg_n % kWave) != 0 ? 1 : 0);
   // FP32 storage holds integer counts only (the host checks), FP64 any value
   constexpr bool kIntData = sizeof(CT) == 4;
-  // Counts are read kPrefetch lane steps ahead of their use, into a ring of
-  // registers: dq[i] holds the count of the next step k with k % kPrefetch ==
+  // Counts are read PF lane steps ahead of their use, into a ring of
+  // registers: dq[i] holds the count of the next step k with k % PF ==
   // i. Reads past a lane's last bin stay inside the counts buffer, which the
-  // host pads by kPrefetch steps. Values stay in the storage type until use.
+  // host pads by PF steps. Values stay in the storage type until use.
   const int64_t idx0 = S.off + S.begin + lane;
   typedef const __attribute__((address_space(1))) CT *GlobalCT;  // global loads, not flat
   const GlobalCT cp = (GlobalCT)(static_cast<const CT *>(S.counts) + idx0);
-  CT dq[kPrefetch];
+  CT dq[PF];
 #pragma unroll
-  for (int i = 0; i < kPrefetch; ++i) dq[i] = CT(0);
+  for (int i = 0; i < PF; ++i) dq[i] = CT(0);
   if constexpr (MODE != kModeModel) {
 #pragma unroll
-    for (int i = 0; i < kPrefetch; ++i) dq[i] = cp[(int64_t)i * kWave];
+    for (int i = 0; i < PF; ++i) dq[i] = cp[(int64_t)i * kWave];
   }
-  // anchors at multiples of kPrefetch steps keep the ring aligned
-  const int every = (S.anchor_every + kPrefetch - 1) / kPrefetch * kPrefetch;
+  // anchors at multiples of PF steps keep the ring aligned
+  const int every = (S.anchor_every + PF - 1) / PF * PF;
   double t = t_first;
 
   // one bin: value, cost term (or model value), gradient, then advance
@@ -991,7 +992,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         } else {
           lane_cost = cost_add<COST, kIntData>(lane_cost, x_cur, N, iv);
         }
-      } else if constexpr (MODE != kModeGrad) {
+      } else if constexpr (!kDeriv) {
         double A = 0.0;
 #pragma unroll
         for (int kt = 0; kt < kMaxT; ++kt) {
@@ -1036,9 +1037,17 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         const double n0E = n0 * E;
         const double N = fma(n0E, onepA, nbkg);
         // hN = -(1/2) d term / dN; the sums below carry that factor and are
-        // scaled by -2 once after the segment
+        // scaled by -2 once after the segment. Jacobian rows carry
+        // sqrt(d^2 term / dN^2) instead: sqrt(2 / v) for chi^2, sqrt(2 d) / N
+        // for the likelihood.
         double hN;
-        if constexpr (COST == MU_COST_CHI2 && kIntData) {
+        if constexpr (MODE == kModeJac) {
+          const double d_cur = kIntData ? x_cur * kCountUnscale : x_cur;
+          if constexpr (COST == MU_COST_CHI2)
+            hN = sqrt(2.0 * (kIntData ? iv : 1.0 / (d_cur > 0.0 ? d_cur : 1.0)));
+          else
+            hN = sqrt(2.0 * d_cur) / N;
+        } else if constexpr (COST == MU_COST_CHI2 && kIntData) {
           const double diff = fma(x_cur, kCountUnscale, -N);
           const double w = diff * iv;
           lane_cost = fma(diff, w, lane_cost);
@@ -1051,12 +1060,27 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
         }
         const double hE = hN * E;     // dN/dN0 = E (1 + A)
         const double hNE = hN * n0E;  // with N0 e^(-t/tau)
-        g[0] = fma(hE, onepA, g[0]);
-        g[1] += hN;
+        // gradient: g_r += x y; Jacobian row: J_r = x y
+        double jr[MODE == kModeJac ? kRS : 1];
+        if constexpr (MODE == kModeJac) {
+#pragma unroll
+          for (int r = 0; r < kRS; ++r) jr[r] = 0.0;
+        }
+        auto put = [&](int r, double x, double y) {
+          if constexpr (MODE == kModeJac)
+            jr[r] = x * y;
+          else
+            g[r] = fma(x, y, g[r]);
+        };
+        put(0, hE, onepA);
+        if constexpr (MODE == kModeJac)
+          jr[1] = hN;
+        else
+          g[1] += hN;
 #pragma unroll
         for (int kt = 0; kt < kMaxT; ++kt) {
           if (kt < n_terms) {
-            g[2 + kt] = fma(hNE * coef[kt], tprod[kt], g[2 + kt]);
+            put(2 + kt, hNE * coef[kt], tprod[kt]);
             const double ca = hNE * gw[kt];
 #pragma unroll
             for (int f = 0; f < kMaxFT; ++f) {
@@ -1066,11 +1090,16 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
 #pragma unroll
                 for (int f2 = 0; f2 < kMaxFT; ++f2)
                   if (f2 != f && f2 < Sh::nf(ts, kt)) others *= val[kt * kMaxFT + f2];
-                g[kArg0 + 2 * s] = fma(others, d0[s], g[kArg0 + 2 * s]);
-                g[kArg0 + 2 * s + 1] = fma(others, d1[s], g[kArg0 + 2 * s + 1]);
+                put(kArg0 + 2 * s, others, d0[s]);
+                put(kArg0 + 2 * s + 1, others, d1[s]);
               }
             }
           }
+        }
+        if constexpr (MODE == kModeJac) {
+          double *row = S.model_out + idx * kJacCols;
+#pragma unroll
+          for (int r = 0; r < kJacCols; ++r) row[r] = r < kRS ? jr[r < kRS ? r : 0] : 0.0;
         }
       }
 
@@ -1171,27 +1200,27 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
     }
     const int k1 = min(n_full, k0 + every);
     int k = k0;
-    // reads of steps k + kPrefetch .. k + 2 kPrefetch - 1 from one pointer
-    GlobalCT nxt = cp + (int64_t)(k0 + kPrefetch) * kWave;
-    for (; k + kPrefetch <= k1; k += kPrefetch, nxt += kPrefetch * kWave) {  // uniform trip count
+    // reads of steps k + PF .. k + 2 PF - 1 from one pointer
+    GlobalCT nxt = cp + (int64_t)(k0 + PF) * kWave;
+    for (; k + PF <= k1; k += PF, nxt += PF * kWave) {  // uniform trip count
 #pragma unroll
-      for (int i = 0; i < kPrefetch; ++i) {
+      for (int i = 0; i < PF; ++i) {
         const double x = (double)dq[i];  // widened (and looked up) first: the load can reuse its register
         const double iv = inv_of(dq[i], x);
         if constexpr (MODE != kModeModel) {
           dq[i] = nxt[i * kWave];
-          // keep the read here, a full kPrefetch steps before its use (the
+          // keep the read here, a full PF steps before its use (the
           // scheduler would otherwise sink it towards the end of the loop)
           __builtin_amdgcn_sched_barrier(0);
         }
         bin_step(cheb_tag, k + i, x, iv);
       }
     }
-    // only the last segment has a tail: under kPrefetch uniform steps, then
+    // only the last segment has a tail: under PF uniform steps, then
     // this lane's ragged extra step
     if (k < k0 + every) {
 #pragma unroll
-      for (int i = 0; i < kPrefetch; ++i)
+      for (int i = 0; i < PF; ++i)
         if (k + i < n_full || (extra && k + i == n_full))
           bin_step(cheb_tag, k + i, (double)dq[i], inv_of(dq[i], (double)dq[i]));
     }
@@ -1206,7 +1235,7 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
   } else {
     run(std::false_type{});
   }
-  if constexpr (MODE == kModeModel) return;
+  if constexpr (MODE == kModeModel || MODE == kModeJac) return;
 
   // wave reduction of the cost (compensated) and the gradient (fixed tree);
   // lane 0 writes the segment's slot
@@ -1284,26 +1313,26 @@ struct ShapeAny {
 
 // One segment with the body of shape Sh, or with the job's own compiled
 // shape under ShapeAny (a wave-uniform switch).
-template <int COST, int MODE, typename CT, typename Sh, int TAB>
+template <int COST, int MODE, typename CT, typename Sh, int TAB, int PF>
 __device__ __forceinline__ void eval_segment_of(const SegIn &S, double *slot, int shape) {
   if constexpr (std::is_same<Sh, ShapeAny>::value) {
     switch (shape) {
-      case kShapeExpCos: eval_segment<COST, MODE, CT, ShapeExpCos, TAB>(S, slot); break;
-      case kShapeGaussCos: eval_segment<COST, MODE, CT, ShapeGaussCos, TAB>(S, slot); break;
-      case kShapeStg: eval_segment<COST, MODE, CT, ShapeStg, TAB>(S, slot); break;
-      case kShapeExpStg: eval_segment<COST, MODE, CT, ShapeExpStg, TAB>(S, slot); break;
-      default: eval_segment<COST, MODE, CT, ShapeExpCosStg, TAB>(S, slot); break;
+      case kShapeExpCos: eval_segment<COST, MODE, CT, ShapeExpCos, TAB, PF>(S, slot); break;
+      case kShapeGaussCos: eval_segment<COST, MODE, CT, ShapeGaussCos, TAB, PF>(S, slot); break;
+      case kShapeStg: eval_segment<COST, MODE, CT, ShapeStg, TAB, PF>(S, slot); break;
+      case kShapeExpStg: eval_segment<COST, MODE, CT, ShapeExpStg, TAB, PF>(S, slot); break;
+      default: eval_segment<COST, MODE, CT, ShapeExpCosStg, TAB, PF>(S, slot); break;
     }
   } else {
     (void)shape;
-    eval_segment<COST, MODE, CT, Sh, TAB>(S, slot);
+    eval_segment<COST, MODE, CT, Sh, TAB, PF>(S, slot);
   }
 }
 
 // The work units (waves) of workgroup b of launch a.
 // TAB = 1: every count of the launch is an integer below kInvTab (the table
 // lookup needs neither clamp nor range test).
-template <int COST, int MODE, typename CT, typename Sh, int TAB>
+template <int COST, int MODE, typename CT, typename Sh, int TAB, int PF = kPrefetch>
 __device__ __forceinline__ void eval_units(const LaunchArgs &a, int b, const double *inv_tab) {
   // each wave is one unit of work; no workgroup barrier after this point
   const int u = __builtin_amdgcn_readfirstlane(b * (kBlock / kWave) + (int)(threadIdx.x / kWave));  // wave-uniform
@@ -1329,7 +1358,7 @@ __device__ __forceinline__ void eval_units(const LaunchArgs &a, int b, const dou
     h = histo_at(J.histos, J.n_histo, pos - vstart);
   }
   int nh = uni(J.n_histo), jb = batch ? uni(J.jbase) : v * nh;
-  if (MODE != kModeModel && jb + h > 0 && pos == vstart + J.histos[h].off) {
+  if ((MODE == kModeCost || MODE == kModeGrad) && jb + h > 0 && pos == vstart + J.histos[h].off) {
     if (lane < kSlot) a.partial[((int64_t)u + jb + h - 1) * kSlot + lane] = 0.0;
   }
   for (;;) {
@@ -1350,7 +1379,7 @@ __device__ __forceinline__ void eval_units(const LaunchArgs &a, int b, const dou
     S.map_row = H.map_row;
     S.anchor_every = a.anchor_every;
     S.inv_tab = inv_tab;
-    eval_segment_of<COST, MODE, CT, Sh, TAB>(S, a.partial + ((int64_t)u + jb + h) * kSlot, uni(J.shape));
+    eval_segment_of<COST, MODE, CT, Sh, TAB, PF>(S, a.partial + ((int64_t)u + jb + h) * kSlot, uni(J.shape));
     pos = seg_end;
     if (pos >= end) return;
     if (++h == nh) {
@@ -1374,12 +1403,12 @@ constexpr bool eval_table() {
   return COST == MU_COST_CHI2 && sizeof(CT) == 4 && MODE != kModeModel;
 }
 
-template <int COST, int MODE, typename CT, typename Sh, int TAB>
+template <int COST, int MODE, typename CT, typename Sh, int TAB, int PF = kPrefetch>
 __global__ __launch_bounds__(kBlock, (eval_min_waves<COST, MODE, Sh, TAB>())) void eval_kernel(LaunchArgs a) {
   constexpr bool kTable = eval_table<COST, MODE, CT>();
   __shared__ __align__(16) double inv_tab[kTable ? kInvTab : 2];
   if constexpr (kTable) load_inv_table(inv_tab, a.inv_src);
-  eval_units<COST, MODE, CT, Sh, TAB>(a, blockIdx.x, inv_tab);
+  eval_units<COST, MODE, CT, Sh, TAB, PF>(a, blockIdx.x, inv_tab);
 }
 
 // A gradient pass and a cost pass over the same dataset and theory in one
@@ -1558,6 +1587,11 @@ hipError_t launch_typed(const LaunchArgs &a, int count_f64, int shape, hipStream
 
 namespace {
 
+// Count prefetch depth of batched launches: the cost pass streams counts
+// from HBM and keeps more reads in flight; the gradient pass (bound by its
+// arithmetic) keeps the registers.
+constexpr int batch_prefetch(int mode) { return mode == kModeCost ? kPrefetchStream : kPrefetch; }
+
 template <int COST, int MODE>
 hipError_t launch_batch_typed(const LaunchArgs &a, int count_f64, int generic, hipStream_t s) {
   dim3 grid((a.n_units + kBlock / kWave - 1) / (kBlock / kWave)), block(kBlock);
@@ -1567,9 +1601,10 @@ hipError_t launch_batch_typed(const LaunchArgs &a, int count_f64, int generic, h
   else if (generic)
     hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeGeneric, 0>), grid, block, 0, s, a);
   else if (kTab && a.counts_in_table)
-    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeAny, kTab ? 1 : 0>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeAny, kTab ? 1 : 0, batch_prefetch(MODE)>), grid, block,
+                       0, s, a);
   else
-    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeAny, 0>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((eval_kernel<COST, MODE, uint32_t, ShapeAny, 0, batch_prefetch(MODE)>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1579,7 +1614,7 @@ int batch_occupancy(int count_f64, int generic) {
   const void *k = (count_f64 || generic)
                       ? (count_f64 ? reinterpret_cast<const void *>(&eval_kernel<COST, MODE, double, ShapeGeneric, 0>)
                                    : reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, ShapeGeneric, 0>))
-                      : reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, ShapeAny, 0>);
+                      : reinterpret_cast<const void *>(&eval_kernel<COST, MODE, uint32_t, ShapeAny, 0, batch_prefetch(MODE)>);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, 0) == hipSuccess ? nb : 0;
 }
 
@@ -1601,6 +1636,14 @@ int eval_batch_blocks_per_cu(int mode, int cost_kind, int count_f64, int generic
                              : batch_occupancy<MU_COST_CHI2, kModeCost>(count_f64, generic);
   return mode == kModeGrad ? batch_occupancy<MU_COST_POISSON, kModeGrad>(count_f64, generic)
                            : batch_occupancy<MU_COST_POISSON, kModeCost>(count_f64, generic);
+}
+
+hipError_t launch_jac(const LaunchArgs &a, int count_f64, int shape, hipStream_t s) {
+  if (a.n_units <= 0) return hipSuccess;
+  if (a.anchor_every < 1 || a.anchor_every > 256 || a.jobs != nullptr || a.n_vec != 1 || !a.tmpl.model_out)
+    return hipErrorInvalidValue;
+  return a.cost_kind == MU_COST_CHI2 ? launch_typed<MU_COST_CHI2, kModeJac>(a, count_f64, shape, s)
+                                     : launch_typed<MU_COST_POISSON, kModeJac>(a, count_f64, shape, s);
 }
 
 hipError_t launch_eval(const LaunchArgs &a, int mode, int count_f64, int shape, hipStream_t s) {

@@ -79,7 +79,15 @@ struct mu_ctx {
   double *d_inv = nullptr;  // [kInvTab] 1 / max(i, 1): source of the kernels' LDS table
   // partial_aux: the gradient pass's slots in mu_chi2_eval_grad
   mu::DevBuf partial, partial_aux, dparams, dout, djobs;
+  mu::DevBuf jac, gram;  // mu_hesse: Jacobian rows, Gram partial blocks
   double *scratch = nullptr;  // this device's allocation-free slots (static_scratch)
+  // kernels of run-time compiled theories, one module per distinct source
+  struct RtcModule {
+    std::string src;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+  };
+  std::vector<RtcModule> rtc;
   mu::HostBuf staging, staging_out;
   std::vector<mu::DevBuf> extra;
   void release_all();
@@ -136,5 +144,7 @@ struct mu_theory {
   int32_t *d_map = nullptr;
   double *d_F = nullptr, *d_f0 = nullptr;
   mu::DevTheory *d_th = nullptr;
+  hipFunction_t rtc_fn = nullptr;  // run-time compiled theory: its kernel (else null)
+  int rtc_refs = 0;                // and the number of its expression references
   void free_dev();
 };

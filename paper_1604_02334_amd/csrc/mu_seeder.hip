@@ -371,13 +371,18 @@ __global__ __launch_bounds__(256) void bias_grad_kernel(const float *dZ, int B, 
   db[n] = s;
 }
 
+// One Adam step on FP32 master weights. The complements 1 - b1 and 1 - b2 come
+// from the host, formed in double like the bias corrections c1 and c2: 1 - b2
+// taken in FP32 from the rounded b2 is off by 1.3e-5 relative, which would
+// scale the first steps by that much against the bias correction.
 __global__ __launch_bounds__(256) void adam_kernel(float *w, const float *g, float *m, float *v, long long n,
-                                                   float lr, float b1, float b2, float eps, float c1, float c2) {
+                                                   float lr, float b1, float b2, float omb1, float omb2, float eps,
+                                                   float c1, float c2) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
   w[i] = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -455,6 +460,7 @@ struct mu_seeder {
   unsigned short *wbf = nullptr;
   long long step = 0;
   int cap = 0;  // batch capacity of the activation buffers
+  int fwd_B = 0, bwd_B = 0;  // batch of the last forward / backward pass (their buffers hold it)
   unsigned short *X[kSeedLayers] = {};   // BF16 input of each layer [cap][K_l]
   float *Z[kSeedLayers] = {};            // FP32 pre-activation / output [cap][N_l]
   float *dZ[kSeedLayers] = {};
@@ -556,6 +562,8 @@ hipError_t refresh_bf16(mu_seeder *S) {
 // Forward pass on S->X[0] for B samples; output in S->Z[last].
 hipError_t forward(mu_seeder *S, int B) {
   hipError_t e = hipSuccess;
+  S->fwd_B = B;
+  S->bwd_B = 0;
   for (int l = 0; l < kSeedLayers && e == hipSuccess; ++l) {
     GemmArgs g;
     std::memset(&g, 0, sizeof g);
@@ -585,6 +593,7 @@ hipError_t forward(mu_seeder *S, int B) {
 // Loss and gradients into S->grads for inputs S->X[0] and targets S->T.
 hipError_t backward(mu_seeder *S, int B) {
   hipStream_t st = S->ctx->stream;
+  S->bwd_B = B;
   const int L = kSeedLayers;
   const int nb = (B * 8 + 255) / 256;
   hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(256), 0, st, S->Z[L - 1], S->T, B, S->dZ[L - 1], S->G[L - 1],
@@ -636,12 +645,14 @@ hipError_t backward(mu_seeder *S, int B) {
 
 hipError_t adam_step(mu_seeder *S, float lr) {
   S->step++;
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float c1 = (float)(1.0 - std::pow(0.9, (double)S->step));
-  const float c2 = (float)(1.0 - std::pow(0.999, (double)S->step));
+  const double b1 = 0.9, b2 = 0.999;
+  const float eps = 1e-8f;
+  const float c1 = (float)(1.0 - std::pow(b1, (double)S->step));
+  const float c2 = (float)(1.0 - std::pow(b2, (double)S->step));
   const long long n = (long long)S->n_params;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S->ctx->stream, S->params,
-                     S->grads, S->m, S->v, n, lr, b1, b2, eps, c1, c2);
+                     S->grads, S->m, S->v, n, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), eps,
+                     c1, c2);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = refresh_bf16(S);
   return e;
@@ -781,6 +792,23 @@ extern "C" mu_status mu_seeder_forward(mu_ctx *ctx, mu_seeder *S, const uint16_t
   hipError_t e = forward(S, B);
   if (e != hipSuccess) return hip_fail(ctx, e, "seeder forward");
   return copy_out(ctx, y, S->Z[kSeedLayers - 1], (size_t)B * 8 * 4, mem);
+}
+
+extern "C" mu_status mu_seeder_layer(mu_ctx *ctx, const mu_seeder *S, int32_t layer, int32_t B, uint16_t *x_in,
+                                     float *z, float *dz, uint16_t *g) {
+  if (!ctx || !S || S->ctx != ctx || layer < 0 || layer >= kSeedLayers || B < 1) return MU_E_ARG;
+  if (B > S->fwd_B || ((dz || g) && B > S->bwd_B)) {
+    set_err(ctx, "mu_seeder_layer: the last forward (backward) pass held %d (%d) samples", S->fwd_B, S->bwd_B);
+    return MU_E_STATE;
+  }
+  hipSetDevice(ctx->device);
+  const size_t K = kDims[layer], N = kDims[layer + 1];
+  mu_status st = MU_OK;
+  if (x_in) st = copy_out(ctx, x_in, S->X[layer], (size_t)B * K * 2, MU_MEM_HOST);
+  if (st == MU_OK && z) st = copy_out(ctx, z, S->Z[layer], (size_t)B * N * 4, MU_MEM_HOST);
+  if (st == MU_OK && dz) st = copy_out(ctx, dz, S->dZ[layer], (size_t)B * N * 4, MU_MEM_HOST);
+  if (st == MU_OK && g) st = copy_out(ctx, g, S->G[layer], (size_t)B * N * 2, MU_MEM_HOST);
+  return st;
 }
 
 extern "C" mu_status mu_seeder_train_step(mu_ctx *ctx, mu_seeder *S, const uint16_t *x_bf16, const float *targets,

@@ -24,8 +24,13 @@ _DECL = {
     "mu_seeder_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mu_seed_infer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "mu_seeder_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "mu_seeder_layer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     "mu_seeder_load": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_void_p)]),
 }
+
+
+DIMS = (1024, 512, 256, 128, 8)  # layer widths of the seeder network
 
 
 class mu_seed_train_opts(C.Structure):
@@ -118,6 +123,19 @@ class Seeder:
                                            1 if update else 0, A.MU_MEM_HOST, loss.ctypes.data),
                self.ctx.h, "mu_seeder_train_step")
         return float(loss[0])
+
+    def layer(self, l, B, backward=False):
+        """Buffers of layer l from the last pass: (BF16 input bits [B][K],
+        FP32 pre-activation [B][N]) and, with backward, (FP32 dZ, BF16 dZ bits)."""
+        K, N = DIMS[l], DIMS[l + 1]
+        x = np.empty((B, K), dtype=np.uint16)
+        z = np.empty((B, N), dtype=np.float32)
+        dz = np.empty((B, N), dtype=np.float32) if backward else None
+        g = np.empty((B, N), dtype=np.uint16) if backward else None
+        _check(_lib().mu_seeder_layer(self.ctx.h, self.h, int(l), int(B), x.ctypes.data, z.ctypes.data,
+                                      dz.ctypes.data if backward else None, g.ctypes.data if backward else None),
+               self.ctx.h, "mu_seeder_layer")
+        return (x, z, dz, g) if backward else (x, z)
 
     def train(self, seed, steps, batch=1024, lr=1e-3, lr_final_frac=0.05, first_sample=0):
         o = mu_seed_train_opts(int(seed), int(first_sample), int(batch), int(steps), float(lr), float(lr_final_frac))

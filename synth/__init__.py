@@ -26,6 +26,7 @@ from .recipes import (  # noqa: F401
     config_c4,
     config_c5_ranges,
     config_paper_shape,
+    config_multi_run,
     draw_counts,
     materialise,
     rng_for,

@@ -159,6 +159,39 @@ def theory_c2(n_det=16, weight=0.3):
     }
 
 
+def config_multi_run():
+    """Two runs fitted together (a multi-run fit): run 0 with 2 histograms of
+    4000 bins of 0.004 us from t0_bin = 10.5, run 1 with 3 histograms of 6000
+    bins of 0.002 us; A(t) = A_r e^(-lambda t) cos(2 pi nu_r t + phi_h) with
+    lambda shared by both runs, A_r and nu_r per run and N0_h, Nbkg_h, phi_h
+    per histogram.  Parameter layout: [lambda, A_0, nu_0, A_1, nu_1] +
+    [N0_h, Nbkg_h, phi_h] per histogram; map row h slots: 0 N0, 1 Nbkg, 2 A,
+    3 lambda, 4 nu, 5 phi (the exp*cos program)."""
+    rng = rng_for(9)
+    runs = [(2, 4000, 0.004, 10.5), (3, 6000, 0.002, 0.0)]
+    rows, histos = [], []
+    h = 0
+    for r, (nh, nb, dt, t0) in enumerate(runs):
+        for _ in range(nh):
+            b = 5 + 3 * h
+            rows.append([b, b + 1, 1 + 2 * r, 0, 2 + 2 * r, b + 2])
+            histos.append(_histo(nb, dt, map_row=h, t0_bin=t0, first=int(t0) + 1))
+            h += 1
+    n_par = 5 + 3 * h
+    th = theory_exp_cos()
+    th["map"] = rows
+    th["n_par"] = n_par
+    th["names"] = ["lambda", "A_0", "nu_0", "A_1", "nu_1"] + [f"{x}_{k}" for k in range(h)
+                                                              for x in ("N0", "Nbkg", "phi")]
+    p = np.zeros(n_par)
+    p[:5] = [0.45, 0.22, 1.1, 0.18, 2.3]
+    for k in range(h):
+        p[5 + 3 * k] = rng.uniform(800.0, 1500.0)
+        p[6 + 3 * k] = rng.uniform(1.0, 10.0)
+        p[7 + 3 * k] = (k % 2) * math.pi + rng.uniform(-0.2, 0.2)
+    return {"name": "multi_run_2x", "theory": th, "histos": histos, "p_true": p, "rng": rng, "seed_k": 9}
+
+
 def theory_paper_eq4(n_det=16):
     """Eq. 4 over n_det detectors with the precession frequency taken from the
     function array, as in Listing 3: nu = f[0] = (gamma_mu / 2 pi) * B.

@@ -162,3 +162,23 @@ def test_fit_edge_cases(ctx):
     # all parameters fixed: nothing moves
     p, _, res = api.fit_batch(ctx, [d], [th], truth[None], fixed=np.ones(6, np.uint8))
     np.testing.assert_array_equal(p[0], truth)
+
+
+def test_multi_run_fit(ctx):
+    """Two runs of different binning and time origin fitted together: lambda
+    shared, amplitude and frequency per run, N0, Nbkg and phase per
+    histogram (one dataset holding both runs' histograms, one map row per
+    histogram).  Against the oracle's minimiser at 1e-6 of max(|p|, sigma)."""
+    _say("multi-run fit")
+    cfg = synth.config_multi_run()
+    th_d, hs = cfg["theory"], cfg["histos"]
+    counts = counts_for(th_d, hs, cfg["p_true"], cfg["rng"])
+    start = cfg["p_true"] * (1.0 + 0.02 * np.cos(np.arange(cfg["p_true"].size)))
+    ref = ofit.fit(th_d, hs, counts, start)
+    th, d = api.Theory(ctx, th_d), api.Data(ctx, hs, counts)
+    p, cov, res = api.fit_batch(ctx, [d], [th], start[None])
+    assert res[0]["status"] == 0, res
+    ok, worst = _agree(p[0], ref["p"], ref["sigma"])
+    assert ok, worst
+    H, c = api.hesse(ctx, d, th, p[0], method="diff")
+    np.testing.assert_allclose(np.sqrt(np.diag(c)), ref["sigma"], rtol=1e-4)

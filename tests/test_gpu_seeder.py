@@ -127,6 +127,99 @@ def test_forward_parity(ctx):
         assert ok, (B, stats)
 
 
+def _scale(X, W, b=None):
+    """sum_k |x_k w_k| (+ |b|): the FP32 accumulation error of a dot product
+    is bounded by K 2^-24 times this."""
+    s = np.abs(X) @ np.abs(W).T
+    return s + np.abs(b)[None, :] if b is not None else s
+
+
+def test_forward_layer_by_layer(ctx):
+    """Each layer on its own: the oracle's FP64 product of the GPU's own BF16
+    input with the BF16 weights (so a rounding flip of an earlier layer
+    cannot propagate) against the GPU's FP32 pre-activation, per element
+    within 1e-4 of sum_k |x_k w_k| + |b| (FP32 sums of K <= 1024 exact BF16
+    products err by at most K 2^-24 of it); the next layer's input is the
+    round-to-nearest-even BF16 of the ReLU of that pre-activation, bit for
+    bit."""
+    _say("seeder forward layer by layer")
+    Ws, bs = osd.init_params(16)
+    bs = [b + np.float32(0.01) * np.arange(b.size, dtype=np.float32) for b in bs]
+    S = Seeder(ctx, _flat(Ws, bs))
+    B = 130
+    xb, _ = _random_inputs(B, 17)
+    y = S.forward(xb)
+    for l in range(4):
+        x_bits, z = S.layer(l, B)
+        if l == 0:
+            np.testing.assert_array_equal(x_bits, xb)
+        X = osd.from_bf16_bits(x_bits).astype(np.float64)
+        W = osd.bf16(Ws[l]).astype(np.float64)
+        ref = X @ W.T + bs[l].astype(np.float64)
+        err = np.abs(z - ref) / _scale(X, W, bs[l].astype(np.float64))
+        assert np.max(err) <= 1e-4, (l, float(np.max(err)))
+        if l < 3:
+            nxt, _ = S.layer(l + 1, B)
+            np.testing.assert_array_equal(nxt, osd.bf16_bits(np.maximum(z, 0.0)))
+        else:
+            np.testing.assert_array_equal(y, z)
+
+
+def test_backward_layer_by_layer_and_adam(ctx):
+    """The backward pass layer by layer from the GPU's own values: the loss
+    gradient of the output, each weight gradient G^T X, bias gradient and
+    masked input gradient (G W) * (Z > 0) against the oracle's FP64 products
+    of the same BF16 operands, within 1e-4 of the sums of |terms|; the BF16
+    copy of each dZ is its round-to-nearest-even rounding.  Then two Adam
+    steps: the oracle's Adam fed the GPU's gradients against the GPU's
+    parameters, element-wise within 1e-6 of |p| + lr (FP32 master weights
+    hold a step of size about lr to FP32 rounding, so a weight near zero is
+    compared on the scale of its step)."""
+    _say("seeder backward layer by layer / adam")
+    Ws, bs = osd.init_params(18)
+    S = Seeder(ctx, _flat(Ws, bs))
+    B = 200
+    xb, _ = _random_inputs(B, 19)
+    T = osd.encode(osd.draw_theta(19, np.arange(B))).astype(np.float32)
+    S.train_step(xb, T, lr=1e-3, update=False)
+    gW, gb = _unflat(S.grads())
+    _, y = S.layer(3, B)
+    _, dY = osd.loss_and_grad(y.astype(np.float64), T)
+    for l in range(3, -1, -1):
+        x_bits, z, dz, g = S.layer(l, B, backward=True)
+        if l == 3:
+            np.testing.assert_allclose(dz, dY, rtol=0, atol=1e-6 * np.max(np.abs(dY)))
+        np.testing.assert_array_equal(g, osd.bf16_bits(dz))
+        G = osd.from_bf16_bits(g).astype(np.float64)
+        X = osd.from_bf16_bits(x_bits).astype(np.float64)
+        dW = G.T @ X
+        err = np.abs(gW[l] - dW) / (np.abs(G).T @ np.abs(X) + 1e-300)
+        assert np.max(err) <= 1e-4, (l, float(np.max(err)))
+        db = dz.astype(np.float64).sum(axis=0)
+        assert np.all(np.abs(gb[l] - db) <= 1e-4 * np.abs(dz).astype(np.float64).sum(axis=0) + 1e-30), l
+        if l > 0:
+            W = osd.bf16(Ws[l]).astype(np.float64)
+            _, zp, dzp, _ = S.layer(l - 1, B, backward=True)
+            ref = (G @ W) * (zp > 0.0)
+            err = np.abs(dzp - ref) / (np.abs(G) @ np.abs(W) + 1e-300)
+            assert np.max(err) <= 1e-4, (l, float(np.max(err)))
+    # Adam from the GPU's own gradients, two steps
+    S2 = Seeder(ctx, _flat(Ws, bs))
+    params = [np.asarray(p, dtype=np.float64) for p in sum(([W.ravel(), b] for W, b in zip(Ws, bs)), [])]
+    m = [np.zeros_like(p) for p in params]
+    v = [np.zeros_like(p) for p in params]
+    for t in (1, 2):
+        S2.train_step(xb, T, lr=1e-3, update=True)
+        gW2, gb2 = _unflat(S2.grads())
+        grads = sum(([w.ravel().astype(np.float64), b.astype(np.float64)] for w, b in zip(gW2, gb2)), [])
+        params = osd.adam(params, grads, m, v, t, 1e-3)
+        got = S2.params().astype(np.float64)
+        ref = np.concatenate(params)
+        bad = np.abs(got - ref) > 1e-6 * (np.abs(ref) + 1e-3)
+        assert not np.any(bad), (t, int(bad.sum()), float(np.max(np.abs(got - ref))))
+        params = [np.asarray(p) for p in np.split(got, np.cumsum([p.size for p in params])[:-1])]
+
+
 def test_backward_and_adam_parity(ctx):
     _say("seeder backward / adam")
     Ws, bs = osd.init_params(12)
@@ -235,6 +328,9 @@ def test_seeded_fits_beat_default_starts(ctx):
     p_ref, cov, r_ref = api.fit_batch(ctx, datas, ths, theta)
     p_s, _, r_s = api.fit_batch(ctx, datas, ths, seeded, want_cov=False)
     p_d, _, r_d = api.fit_batch(ctx, datas, ths, default, want_cov=False)
+    # a stronger non-learned start: nu, A, phi from the periodogram peak
+    pgram = _periodogram_starts(counts, default[:, 0], default[:, 1])
+    p_g, _, r_g = api.fit_batch(ctx, datas, ths, pgram, want_cov=False)
 
     def success(p):
         good = 0
@@ -250,8 +346,37 @@ def test_seeded_fits_beat_default_starts(ctx):
             good += bool(np.all(d <= 1e-6 * np.maximum(np.abs(b), sig)))
         return good
 
-    s_seed, s_def = success(p_s), success(p_d)
-    print(f"[result] ok {ok.mean():.3f} seeded {s_seed}/{n} default {s_def}/{n} "
-          f"fcn seeded {np.mean([r['n_fcn'] for r in r_s]):.1f} default {np.mean([r['n_fcn'] for r in r_d]):.1f}",
-          flush=True)
+    s_seed, s_def, s_pg = success(p_s), success(p_d), success(p_g)
+    print(f"[result] ok {ok.mean():.3f} seeded {s_seed}/{n} default {s_def}/{n} periodogram {s_pg}/{n} "
+          f"fcn seeded {np.mean([r['n_fcn'] for r in r_s]):.1f} default {np.mean([r['n_fcn'] for r in r_d]):.1f} "
+          f"periodogram {np.mean([r['n_fcn'] for r in r_g]):.1f}", flush=True)
     assert s_seed > s_def
+    assert s_pg > s_def  # the periodogram baseline is a real baseline
+
+
+def _periodogram_starts(counts, n0, nbkg, tau=synth.TAU_MU, dt=0.001, rebin=8):
+    """nu, A, phi from the peak of the periodogram of the rebinned asymmetry
+    (c_b - 8 Nbkg) / (8 N0 ebar_b) - 1 weighted by the expected signal
+    8 N0 ebar_b; lambda 0.5; N0, Nbkg as given."""
+    n, nb = counts.shape
+    m = nb // rebin
+    c = counts.astype(np.float64).reshape(n, m, rebin).sum(axis=2)
+    r = math.exp(-dt / tau)
+    b = np.arange(m, dtype=np.float64)
+    ebar = np.exp(-(rebin * dt / tau) * b) * ((1.0 - r ** rebin) / (rebin * (1.0 - r)))
+    w = rebin * n0[:, None] * ebar[None, :]
+    a = (c - rebin * nbkg[:, None]) / w - 1.0
+    t = rebin * dt * b + 0.5 * (rebin - 1) * dt
+    pad = 8 * m
+    spec = np.fft.rfft(w * a, n=pad, axis=1)
+    freqs = np.fft.rfftfreq(pad, d=rebin * dt)
+    spec[:, freqs < 0.05] = 0.0
+    k = np.argmax(np.abs(spec), axis=1)
+    df = freqs[1] - freqs[0]
+    out = np.zeros((n, 6))
+    for i in range(n):
+        grid = freqs[k[i]] + df * np.linspace(-1.0, 1.0, 41)
+        S = (w[i] * a[i]) @ np.exp(-2j * np.pi * np.outer(t, grid))
+        j = int(np.argmax(np.abs(S)))
+        out[i] = [n0[i], nbkg[i], min(2.0 * abs(S[j]) / w[i].sum(), 0.5), 0.5, grid[j], float(np.angle(S[j]))]
+    return out

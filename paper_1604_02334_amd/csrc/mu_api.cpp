@@ -372,10 +372,11 @@ extern "C" mu_status mu_histo_check(const mu_histo *h, int32_t n_histo, char *ms
 }
 
 // The gradient merge plan of (th, this dataset); layout next to kPlanHead.
-mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out) {
+mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out, int *lds) {
   for (const Plan &p : plans)
     if (p.theory_id == th->id) {
       *out = p.d;
+      if (lds) *lds = p.lds;
       return MU_OK;
     }
   const DevTheory &T = th->h;
@@ -427,7 +428,10 @@ mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out) {
   buf[2] = (int32_t)stride;
   for (int i = 0; i < na; ++i) buf[kPlanAct + i] = act[i];
   for (int c = 0; c < n_chunks; ++c) std::copy(blocks[c].begin(), blocks[c].end(), buf.begin() + kPlanHead + c * stride);
-  Plan p{th->id, nullptr};
+  // the merge's dynamic LDS: acc_s, acc_c [n_par], srt, fsrt [min(n_histo,
+  // kMergeChunk) na] doubles, then the plan block [stride] ints
+  const size_t merge_lds = 8 * (2 * (size_t)n_par + 2 * (size_t)std::min(n_histo, kMergeChunk) * na) + 4 * stride;
+  Plan p{th->id, nullptr, (int)((merge_lds + 15) / 16 * 16)};
   hipError_t e = hipMalloc(&p.d, buf.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(p.d, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -436,6 +440,7 @@ mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out) {
   }
   plans.push_back(p);
   *out = p.d;
+  if (lds) *lds = p.lds;
   return MU_OK;
 }
 
@@ -879,6 +884,7 @@ static mu_status check_eval_args(mu_ctx *ctx, int cost_kind, unsigned mem, int32
 struct Pending {
   LaunchArgs a;
   int mode = 0, n_vec = 0, shape = 0, f64 = 0;
+  int merge_lds = 0;  // dynamic LDS bytes of the merge (gradient mode)
   hipFunction_t rtc = nullptr;  // run-time compiled theory's kernel
 };
 
@@ -914,7 +920,8 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
     if ((st = partial.ensure(ctx, n_slots * kSlot * sizeof(double), false)) != MU_OK) return st;
   }
   const int32_t *plan = nullptr;
-  if (mode == kModeGrad && (st = d->grad_plan(th, &plan)) != MU_OK) return st;
+  int merge_lds = 0;
+  if (mode == kModeGrad && (st = d->grad_plan(th, &plan, &merge_lds)) != MU_OK) return st;
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.tmpl.th = th->d_th;
@@ -949,6 +956,7 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
   pend.shape = shape;
   pend.f64 = d->f64;
   pend.rtc = th->rtc_fn;
+  pend.merge_lds = merge_lds;
   if (!launch) return MU_OK;
   if (no_alloc) {  // no timing events (they are created on demand)
     hipError_t e = launch_pending(pend, mode, s);
@@ -967,7 +975,8 @@ static mu_status eval_launch(mu_ctx *ctx, mu_data *d, const mu_theory *th, int c
 static mu_status eval_merge(mu_ctx *ctx, const Pending &pend, hipStream_t s) {
   if (pend.mode == kModeModel) return MU_OK;
   const int ti = ctx->time_begin(MU_TIME_MERGE, s);
-  hipError_t e = launch_merge(pend.a, pend.mode, pend.n_vec, s);
+  const bool narrow = pend.n_vec >= kNarrowJobs && pend.a.tmpl.n_histo <= kNarrowHisto;
+  hipError_t e = launch_merge(pend.a, pend.mode, pend.n_vec, pend.merge_lds, narrow, s);
   ctx->time_end(ti, s);
   return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "merge launch");
 }
@@ -1101,7 +1110,7 @@ mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int 
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "evaluation launch");
   const int ti = ctx->time_begin(MU_TIME_MERGE, ctx->stream);
-  e = launch_merge_grad_cost(pg_.a, n_grad, pc_.a, n_cost, ctx->stream);
+  e = launch_merge_grad_cost(pg_.a, n_grad, pc_.a, n_cost, pg_.merge_lds, ctx->stream);
   ctx->time_end(ti, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
   if (mem == MU_MEM_HOST) {
@@ -1160,7 +1169,8 @@ extern "C" mu_status mu_chi2_eval_static(mu_ctx *ctx, const mu_data *data, const
   st = eval_launch(ctx, const_cast<mu_data *>(data), th, cost_kind, params, n_vec, cost, cost_per_histo, nullptr,
                    nullptr, kModeCost, ctx->stream, slots, pend, true, 0, true);
   if (st != MU_OK) return st;
-  hipError_t e = launch_merge(pend.a, pend.mode, pend.n_vec, ctx->stream);
+  const bool narrow = pend.n_vec >= kNarrowJobs && pend.a.tmpl.n_histo <= kNarrowHisto;
+  hipError_t e = launch_merge(pend.a, pend.mode, pend.n_vec, pend.merge_lds, narrow, ctx->stream);
   return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "merge launch");
 }
 
@@ -1323,9 +1333,13 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
   }
   // gradient merge plans first (they may upload)
   std::vector<const int32_t *> plans(n_jobs, nullptr);
+  int merge_lds = 0;
   if (grad)
-    for (int j = 0; j < n_jobs; ++j)
-      if ((st = const_cast<mu_data *>(data[j])->grad_plan(th[j], &plans[j])) != MU_OK) return st;
+    for (int j = 0; j < n_jobs; ++j) {
+      int lds = 0;
+      if ((st = const_cast<mu_data *>(data[j])->grad_plan(th[j], &plans[j], &lds)) != MU_OK) return st;
+      merge_lds = std::max(merge_lds, lds);
+    }
   ctx->wait_staging();
   char *up = static_cast<char *>(ctx->staging.ptr);
   char *dup = static_cast<char *>(ctx->djobs.ptr);
@@ -1424,7 +1438,10 @@ mu_status run_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, con
     m.jobs = reinterpret_cast<const DevJob *>(dup);
     m.partial = part;
     const int ti = ctx->time_begin(MU_TIME_MERGE, ctx->stream);
-    e = launch_merge(m, mode, n_jobs, ctx->stream);
+    int max_histo = 0;
+    for (int j = 0; j < n_jobs; ++j) max_histo = std::max(max_histo, data[j]->n_histo);
+    const bool narrow = n_jobs >= kNarrowJobs && max_histo <= kNarrowHisto;
+    e = launch_merge(m, mode, n_jobs, merge_lds, narrow, ctx->stream);
     ctx->time_end(ti, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
   }

@@ -510,7 +510,11 @@ __device__ double sum_slot_pairs(const double *P, int k0, int k1) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = pair_add(acc[u], v[u]);
   }
-  for (int u = 0; k < k1; ++k, ++u) acc[u] = pair_add(acc[u], Pair{P[(int64_t)k * kSlot], P[(int64_t)k * kSlot + 1]});
+  // the rest (fewer than 8), slot k + u into acc[u]: unrolled, so the
+  // accumulators stay in registers
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (k + u < k1) acc[u] = pair_add(acc[u], Pair{P[(int64_t)(k + u) * kSlot], P[(int64_t)(k + u) * kSlot + 1]});
   Pair t = acc[0];
 #pragma unroll
   for (int u = 1; u < 8; ++u) t = pair_add(t, acc[u]);
@@ -538,14 +542,17 @@ struct SlotMap {
   }
 };
 
-template <int MODE>
+template <int MODE, int NT>
 __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   // Phase A issues every load that depends on nothing else (the slot span,
   // the plan's header and active scalars, the first chunk's histogram
   // records); phase B issues the cost slots, the first chunk's gradient slots
   // and its plan block together. Later histogram chunks add two rounds each.
   constexpr int HC = kMergeChunk;
-  constexpr int kWaves = kBlock / 64;
+  constexpr int kWaves = NT / 64;
+  // threads of phase A's independent loads: spread over the waves when there
+  // are several
+  constexpr int kTSpan = NT >= 256 ? 64 : 1, kTAct = NT >= 256 ? 128 : 2, kTHdr = NT >= 256 ? 192 : 2 + kRS;
   constexpr bool G = MODE == kModeGrad;
   __shared__ Pair red[kWaves];
   __shared__ int span_s[2];
@@ -576,15 +583,19 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   // order within a run), or in the list of function entries fsrt (entry
   // order). Each parameter then sums its run and the function entries in that
   // fixed order, whatever the timing.
-  __shared__ double srt[G ? HC * kRS : 1], fsrt[G ? HC * kRS : 1];
-  __shared__ int pl[G ? kPlanBlockMax : 1];
+  // The gradient mode's arrays live in the launch's dynamic LDS, sized by the
+  // host from the launch's plans (merge_lds_bytes): acc_s and acc_c [n_par],
+  // then srt and fsrt [min(n_histo, HC) na], then pl [plan stride]. Small
+  // jobs then leave room for many workgroups per CU.
   __shared__ int act[kRS], hdr[3];
-  __shared__ double acc_s[G ? MU_MAX_PAR : 1];
-  __shared__ double acc_c[G ? MU_MAX_PAR : 1];
+  extern __shared__ __align__(16) double merge_dyn[];
+  double *acc_s = merge_dyn, *acc_c = merge_dyn + n_par;
+  double *srt = nullptr, *fsrt = nullptr;
+  int *pl = nullptr;
 
   auto stage_ranges = [&](int h0) {
     const int nh = min(HC, J.n_histo - h0);
-    for (int hh = tid; hh < nh; hh += kBlock) {
+    for (int hh = tid; hh < nh; hh += NT) {
       int k0, k1;
       sm.range(h0 + hh, k0, k1);
       rk0[hh] = k0;
@@ -595,18 +606,18 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   auto chunk_entries = [&](int h0) {
     const int nh = min(HC, J.n_histo - h0);
     if (J.histo_out)
-      for (int hh = tid; hh < nh; hh += kBlock) J.histo_out[h0 + hh] = sum_slot_pairs(P, rk0[hh], rk1[hh]);
+      for (int hh = tid; hh < nh; hh += NT) J.histo_out[h0 + hh] = sum_slot_pairs(P, rk0[hh], rk1[hh]);
     if constexpr (G) {
       const int na = hdr[0], stride = hdr[2];
       const int32_t *blk = J.plan + kPlanHead + (int64_t)(h0 / HC) * stride;
-      for (int q = tid; q < stride; q += kBlock) pl[q] = blk[q];
+      for (int q = tid; q < stride; q += NT) pl[q] = blk[q];
       const int32_t *dst = blk + 3 + n_par;
       // S adjacent lanes per entry (up to 8, while the entries fill the
       // workgroup) take its slots in turn; a fixed butterfly combines them
       const int ne = nh * na;
       int S = 1;
-      while (S < 8 && ne * S * 2 <= kBlock) S <<= 1;
-      for (int base = 0; base < ne * S; base += kBlock) {  // uniform: every lane reaches the shuffles
+      while (S < 8 && ne * S * 2 <= NT) S <<= 1;
+      for (int base = 0; base < ne * S; base += NT) {  // uniform: every lane reaches the shuffles
         const int t = base + tid, e = t / S, sl = t % S;
         const bool on = t < ne * S;
         Pair v{0.0, 0.0};
@@ -630,7 +641,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
     if constexpr (G) {
       const int ne = min(HC, J.n_histo - h0) * hdr[0], n_fe = pl[1];
       const int *koff = pl + 2, *fi = pl + 3 + n_par + ne;
-      for (int k = tid; k < n_par; k += kBlock) {
+      for (int k = tid; k < n_par; k += NT) {
         Pair q{acc_s[k], acc_c[k]};
         for (int j = koff[k]; j < koff[k + 1]; ++j) q = pair_add(q, Pair{srt[j], 0.0});
         for (int f = 0; f < n_fe; ++f) q = pair_add(q, Pair{fsrt[f] * th->F[(int64_t)fi[f] * n_par + k], 0.0});
@@ -646,26 +657,32 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
     sm.range(0, k0, k1);
     span_s[0] = k0;
   }
-  if (tid == 64) {
+  if (tid == kTSpan) {
     int k0, k1;
     sm.range(J.n_histo - 1, k0, k1);
     span_s[1] = k1;
   }
   if constexpr (G) {
-    if (tid >= 128 && tid < 128 + kRS) act[tid - 128] = J.plan[kPlanAct + tid - 128];
-    if (tid >= 192 && tid < 195) hdr[tid - 192] = J.plan[tid - 192];
-    for (int k = tid; k < n_par; k += kBlock) {
+    if (tid >= kTAct && tid < kTAct + kRS) act[tid - kTAct] = J.plan[kPlanAct + tid - kTAct];
+    if (tid >= kTHdr && tid < kTHdr + 3) hdr[tid - kTHdr] = J.plan[tid - kTHdr];
+    for (int k = tid; k < n_par; k += NT) {
       acc_s[k] = 0.0;
       acc_c[k] = 0.0;
     }
   }
   if (need_chunks) stage_ranges(0);
   __syncthreads();
+  if constexpr (G) {
+    const int ne_max = min(J.n_histo, HC) * hdr[0];
+    srt = acc_c + n_par;
+    fsrt = srt + ne_max;
+    pl = reinterpret_cast<int *>(fsrt + ne_max);
+  }
 
   // ---- phase B: total cost (strided fixed assignment of slots to threads,
   // then a tree) and the first chunk
   Pair acc{0.0, 0.0};
-  for (int k = span_s[0] + tid; k < span_s[1]; k += kBlock)
+  for (int k = span_s[0] + tid; k < span_s[1]; k += NT)
     acc = pair_add(acc, Pair{P[(int64_t)k * kSlot], P[(int64_t)k * kSlot + 1]});
   if (need_chunks) chunk_entries(0);
   acc = wave_pair_sum(acc);
@@ -688,7 +705,7 @@ __device__ void merge_job(const LaunchArgs &a, const DevJob &J, int job) {
   }
   if constexpr (G) {
     __syncthreads();
-    for (int k = tid; k < n_par; k += kBlock) J.grad_out[k] = pair_value(Pair{acc_s[k], acc_c[k]});
+    for (int k = tid; k < n_par; k += NT) J.grad_out[k] = pair_value(Pair{acc_s[k], acc_c[k]});
   }
 }
 
@@ -1430,7 +1447,7 @@ __global__ __launch_bounds__(kBlock, 4) void eval_grad_cost_kernel(LaunchArgs g,
 // One workgroup per job: fixed-order merge of the job's slots.  It runs as
 // its own launch after the evaluation kernel, whose completion makes every
 // slot visible; no fences or atomics are needed inside the evaluation kernel.
-template <int MODE>
+template <int MODE, int NT = kBlock>
 __device__ __forceinline__ void merge_block(const LaunchArgs &a, int job) {
   DevJob J;
   if (a.jobs == nullptr) {
@@ -1442,12 +1459,14 @@ __device__ __forceinline__ void merge_block(const LaunchArgs &a, int job) {
   } else {
     J = a.jobs[job];
   }
-  merge_job<MODE>(a, J, job);
+  merge_job<MODE, NT>(a, J, job);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void merge_kernel(LaunchArgs a) {
-  merge_block<MODE>(a, blockIdx.x);
+// NT threads per job: one wave for launches of many small jobs (more jobs
+// in flight per CU), else four.
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void merge_kernel(LaunchArgs a) {
+  merge_block<MODE, NT>(a, blockIdx.x);
 }
 
 // Merges of two launches in one: workgroups [0, n_first) merge the jobs of
@@ -1552,20 +1571,28 @@ hipError_t launch_eval_grad_cost(const LaunchArgs &g, const LaunchArgs &c, int c
   return launch_grad_cost_typed<MU_COST_CHI2>(g, c, shape, s);
 }
 
-hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s) {
+hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, int lds_bytes, bool narrow, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  dim3 grid(n_jobs), block(kBlock);
-  if (mode == kModeGrad)
-    hipLaunchKernelGGL((merge_kernel<kModeGrad>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((merge_kernel<kModeCost>), grid, block, 0, s, a);
+  dim3 grid(n_jobs), block(narrow ? kWave : kBlock);
+  if (mode == kModeGrad) {
+    if (narrow)
+      hipLaunchKernelGGL((merge_kernel<kModeGrad, kWave>), grid, block, (size_t)lds_bytes, s, a);
+    else
+      hipLaunchKernelGGL((merge_kernel<kModeGrad, kBlock>), grid, block, (size_t)lds_bytes, s, a);
+  } else {
+    if (narrow)
+      hipLaunchKernelGGL((merge_kernel<kModeCost, kWave>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((merge_kernel<kModeCost, kBlock>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, hipStream_t s) {
+hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, int lds_bytes,
+                                  hipStream_t s) {
   if (n_grad <= 0 || n_cost <= 0) return hipErrorInvalidValue;
   dim3 grid(n_grad + n_cost), block(kBlock);
-  hipLaunchKernelGGL((merge2_kernel<kModeGrad, kModeCost>), grid, block, 0, s, g, n_grad, c);
+  hipLaunchKernelGGL((merge2_kernel<kModeGrad, kModeCost>), grid, block, (size_t)lds_bytes, s, g, n_grad, c);
   return hipGetLastError();
 }
 

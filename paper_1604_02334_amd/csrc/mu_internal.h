@@ -45,8 +45,10 @@ int eval_blocks_per_cu(int mode, int cost_kind, int count_f64, int shape);
 hipError_t launch_eval_batch(const LaunchArgs &a, int mode, int count_f64, int generic, hipStream_t s);
 int eval_batch_blocks_per_cu(int mode, int cost_kind, int count_f64, int generic);
 // Merge the slots of jobs [0, n_jobs) of `a` (uniform or batched).
-hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, hipStream_t s);
+// narrow: one wave per job (launches of many jobs of few histograms each).
+hipError_t launch_merge(const LaunchArgs &a, int mode, int n_jobs, int lds_bytes, bool narrow, hipStream_t s);
 // One launch merging a gradient launch's n_grad jobs and a cost launch's n_cost jobs.
-hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, hipStream_t s);
+hipError_t launch_merge_grad_cost(const LaunchArgs &g, int n_grad, const LaunchArgs &c, int n_cost, int lds_bytes,
+                                  hipStream_t s);
 
 }  // namespace mu

@@ -128,9 +128,10 @@ struct mu_data {
   struct Plan {
     uint64_t theory_id;
     int32_t *d;
+    int lds;  // dynamic LDS bytes its merge needs
   };
   std::vector<Plan> plans;
-  mu_status grad_plan(const mu_theory *th, const int32_t **out);
+  mu_status grad_plan(const mu_theory *th, const int32_t **out, int *lds = nullptr);
   void free_dev();
 };
 

@@ -63,6 +63,9 @@ constexpr int kRefNone = -1;
 // in entry order, that feeds a function) and fi[n_fe] (the function of each
 // function entry).
 constexpr int kMergeChunk = 32;  // histograms per merge chunk
+// merges of at least kNarrowJobs jobs of at most kNarrowHisto histograms
+// each take one wave per job
+constexpr int kNarrowJobs = 256, kNarrowHisto = 4;
 constexpr int kPlanAct = 4;
 constexpr int kPlanHead = 64;
 constexpr int kPlanBlockMax = (3 + MU_MAX_PAR + 2 * kMergeChunk * kRS + 63) / 64 * 64;

@@ -137,12 +137,23 @@ __global__ __launch_bounds__(256) void gen_kernel(unsigned long long seed, unsig
   draw_theta(seed, idx, th);
   const double w = kTwoPi * th[4];
   const int nb = fine ? kFine : kCoarse, sub = fine ? 1 : kRebin;
+  // a rebinned bin's fine bins: the first evaluated directly, the others by
+  // one fine step of each factor (geometric decays, rotation)
+  const double r1 = exp(-kDtFine / kTau), r2 = exp(-th[3] * kDtFine);
+  double sw, cw;
+  sincos(w * kDtFine, &sw, &cw);
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double t0 = (double)(b * sub) * kDtFine;
+    double e1 = exp(-t0 / kTau), e2 = exp(-th[3] * t0), sn, cs;
+    sincos(w * t0 + th[5], &sn, &cs);
     double mu = 0.0;
     for (int q = 0; q < sub; ++q) {
-      const double t = (double)(b * sub + q) * kDtFine;
-      const double N = th[0] * exp(-t / kTau) * (1.0 + th[2] * exp(-th[3] * t) * cos(w * t + th[5])) + th[1];
-      mu += N;
+      mu += th[0] * e1 * (1.0 + th[2] * e2 * cs) + th[1];
+      e1 *= r1;
+      e2 *= r2;
+      const double c2 = cs * cw - sn * sw;
+      sn = sn * cw + cs * sw;
+      cs = c2;
     }
     if (mu_out) mu_out[(size_t)s * nb + b] = mu;
     if (counts) counts[(size_t)s * nb + b] = (float)poisson(mu, seed, idx, (unsigned)(fine ? 0x10000 + b : b));
@@ -426,39 +437,63 @@ __global__ void loss_final_kernel(const double *partial, int n, int B, float *lo
   *loss = (float)(s / B);
 }
 
-// db[n] = sum_b dZ[b][n] in a fixed order, in two launches: workgroup (x, z)
-// sums columns [64 x, 64 x + 64) over rows [64 z, 64 z + 64) (four row
-// groups of 16 rows, then the groups in order) into part[z][n]; then
-// bias_grad_final_kernel sums the row slices in order.
+// db[n] = sum_b dZ[b][n] in a fixed order: 64-row slices, four row groups of
+// 16 rows each combined in order, then the slices in order.
 constexpr int kBiasRows = 64;
-__global__ __launch_bounds__(256) void bias_grad_kernel(const float *dZ, int B, int N, float *part) {
+
+// The bias gradients of every layer in one pair of launches (after the
+// backward pass, whose dZ of each layer stays in its own buffer): column
+// block x of the layers' concatenated columns, row slice y, as above; then
+// every column's slices in order.
+struct BiasAll {
+  const float *dZ[kSeedLayers];
+  float *db[kSeedLayers];
+  int N[kSeedLayers];
+  int col0[kSeedLayers + 1];  // first concatenated column of each layer
+};
+
+__global__ __launch_bounds__(256) void bias_grad_all_kernel(BiasAll a, int B, float *part) {
   __shared__ float red[4][64];
   const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int n = blockIdx.x * 64 + c;
+  const int g = blockIdx.x * 64 + c;  // concatenated column
+  int l = 0;
+  while (l + 1 < kSeedLayers && g >= a.col0[l + 1]) ++l;
+  const int n = g - a.col0[l], N = a.N[l];
   const int b0 = blockIdx.y * kBiasRows, b1 = min(B, b0 + kBiasRows);
+  const bool on = g < a.col0[kSeedLayers];
   float s = 0.0f;
-  if (n < N)
-    for (int b = b0 + rg; b < b1; b += 4) s += dZ[(size_t)b * N + n];
+  if (on)
+    for (int b = b0 + rg; b < b1; b += 4) s += a.dZ[l][(size_t)b * N + n];
   red[rg][c] = s;
   __syncthreads();
-  if (rg == 0 && n < N) part[(size_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  if (rg == 0 && on) part[(size_t)blockIdx.y * a.col0[kSeedLayers] + g] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-__global__ __launch_bounds__(256) void bias_grad_final_kernel(const float *part, int n_slices, int N, float *db) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
-  float s = part[n];
-  for (int z = 1; z < n_slices; ++z) s += part[(size_t)z * N + n];
-  db[n] = s;
+__global__ __launch_bounds__(256) void bias_grad_all_final_kernel(BiasAll a, const float *part, int n_slices) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int tot = a.col0[kSeedLayers];
+  if (g >= tot) return;
+  int l = 0;
+  while (l + 1 < kSeedLayers && g >= a.col0[l + 1]) ++l;
+  float s = part[g];
+  for (int z = 1; z < n_slices; ++z) s += part[(size_t)z * tot + g];
+  a.db[l][g - a.col0[l]] = s;
 }
 
 // One Adam step on FP32 master weights. The complements 1 - b1 and 1 - b2 come
 // from the host, formed in double like the bias corrections c1 and c2: 1 - b2
 // taken in FP32 from the rounded b2 is off by 1.3e-5 relative, which would
 // scale the first steps by that much against the bias correction.
+// Where each layer's weights sit in the parameters and in their BF16 copy.
+struct WeightMap {
+  long long off_w[kSeedLayers], off_wbf[kSeedLayers], size[kSeedLayers];
+};
+
+// It also writes the BF16 copy of each updated weight (the next forward
+// pass's operand), so no conversion launches follow.
 __global__ __launch_bounds__(256) void adam_kernel(float *w, const float *g, float *m, float *v, long long n,
                                                    float lr, float b1, float b2, float omb1, float omb2, float eps,
-                                                   float c1, float c2) {
+                                                   float c1, float c2, WeightMap wm, unsigned short *wbf) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -466,7 +501,11 @@ __global__ __launch_bounds__(256) void adam_kernel(float *w, const float *g, flo
   const float vi = b2 * v[i] + omb2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  w[i] = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+#pragma unroll
+  for (int l = 0; l < kSeedLayers; ++l)
+    if (i >= wm.off_w[l] && i < wm.off_w[l] + wm.size[l]) wbf[wm.off_wbf[l] + (i - wm.off_w[l])] = f2bf(wi);
 }
 
 __global__ __launch_bounds__(256) void to_bf16_kernel(const float *src, unsigned short *dst, long long n) {
@@ -670,7 +709,7 @@ mu_status mu_seeder::ensure(int B) {
   al((void **)&srcs, (size_t)B * sizeof(void *));
   const size_t wsf = gemm_ws_floats(B);
   al((void **)&ws, wsf * 4);
-  al((void **)&bpart, (size_t)((B + kBiasRows - 1) / kBiasRows) * kDims[1] * 4);
+  al((void **)&bpart, (size_t)((B + kBiasRows - 1) / kBiasRows) * (kDims[1] + kDims[2] + kDims[3] + kDims[4]) * 4);
   if (e != hipSuccess) {
     free_acts();
     set_err(ctx, "seeder activation buffers for a batch of %d: %s", B, hipGetErrorString(e));
@@ -750,11 +789,6 @@ hipError_t backward(mu_seeder *S, int B) {
     g.epi = kEpiStore;
     g.C = S->grads + S->off_w[l];
     if ((e = gemm(g, S->ws, S->ws_floats, st)) != hipSuccess) break;
-    const int n_slices = (B + kBiasRows - 1) / kBiasRows;
-    hipLaunchKernelGGL(bias_grad_kernel, dim3((N + 63) / 64, n_slices), dim3(256), 0, st, S->dZ[l], B, N,
-                       S->bpart);
-    hipLaunchKernelGGL(bias_grad_final_kernel, dim3((N + 255) / 256), dim3(256), 0, st, S->bpart, n_slices, N,
-                       S->grads + S->off_b[l]);
     if (l > 0) {
       // dX[b][k] = sum_n G[b][n] W[n][k], masked by the previous layer's ReLU
       GemmArgs d;
@@ -776,7 +810,20 @@ hipError_t backward(mu_seeder *S, int B) {
     }
     if (e == hipSuccess) e = hipGetLastError();
   }
-  return e;
+  if (e != hipSuccess) return e;
+  // bias gradients of all layers
+  BiasAll ba;
+  ba.col0[0] = 0;
+  for (int l = 0; l < L; ++l) {
+    ba.dZ[l] = S->dZ[l];
+    ba.db[l] = S->grads + S->off_b[l];
+    ba.N[l] = kDims[l + 1];
+    ba.col0[l + 1] = ba.col0[l] + kDims[l + 1];
+  }
+  const int n_slices = (B + kBiasRows - 1) / kBiasRows, tot = ba.col0[L];
+  hipLaunchKernelGGL(bias_grad_all_kernel, dim3((tot + 63) / 64, n_slices), dim3(256), 0, st, ba, B, S->bpart);
+  hipLaunchKernelGGL(bias_grad_all_final_kernel, dim3((tot + 255) / 256), dim3(256), 0, st, ba, S->bpart, n_slices);
+  return hipGetLastError();
 }
 
 hipError_t adam_step(mu_seeder *S, float lr) {
@@ -786,12 +833,16 @@ hipError_t adam_step(mu_seeder *S, float lr) {
   const float c1 = (float)(1.0 - std::pow(b1, (double)S->step));
   const float c2 = (float)(1.0 - std::pow(b2, (double)S->step));
   const long long n = (long long)S->n_params;
+  WeightMap wm;
+  for (int l = 0; l < kSeedLayers; ++l) {
+    wm.off_w[l] = (long long)S->off_w[l];
+    wm.off_wbf[l] = (long long)S->off_wbf[l];
+    wm.size[l] = (long long)kDims[l] * kDims[l + 1];
+  }
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S->ctx->stream, S->params,
                      S->grads, S->m, S->v, n, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), eps,
-                     c1, c2);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = refresh_bf16(S);
-  return e;
+                     c1, c2, wm, S->wbf);
+  return hipGetLastError();
 }
 
 mu_status copy_in(mu_ctx *ctx, void *dst, const void *src, size_t bytes, unsigned mem) {

@@ -55,9 +55,16 @@ struct Node {
   std::vector<int> kids;
 };
 
+// Limits that keep the recursive-descent parser's stack and the generated
+// kernel bounded.
+constexpr int kMaxNest = 200;
+constexpr size_t kMaxExprLen = 1 << 16;
+constexpr size_t kMaxNodes = 4096;  // bounds the tree's depth for the recursive emitter
+
 struct Parser {
   const char *s;
   size_t i = 0;
+  int nest = 0;  // unary() frames open (every recursion passes through unary)
   std::vector<Node> nodes;
   std::string err;
 
@@ -69,6 +76,7 @@ struct Parser {
     return false;
   }
   int add(Node n) {
+    if (nodes.size() >= kMaxNodes) return fail("more than " + std::to_string(kMaxNodes) + " operations"), -1;
     nodes.push_back(std::move(n));
     return (int)nodes.size() - 1;
   }
@@ -113,6 +121,13 @@ struct Parser {
     }
   }
   int unary() {
+    if (nest >= kMaxNest) return fail("nesting deeper than " + std::to_string(kMaxNest)), -1;
+    ++nest;
+    const int r = unary_body();
+    --nest;
+    return r;
+  }
+  int unary_body() {
     if (eat('-')) {
       const int a = unary();
       if (a < 0) return -1;
@@ -307,6 +322,10 @@ mu_status parse_expr(const mu_expr_theory_desc *d, Parsed &P, std::string &src, 
   if ((d->n0.kind == MU_REF_LIT && !std::isfinite(d->n0.literal)) ||
       (d->nbkg.kind == MU_REF_LIT && !std::isfinite(d->nbkg.literal))) {
     why = "a literal N0 or Nbkg is not finite";
+    return MU_E_ARG;
+  }
+  if (std::strlen(d->asymmetry) > kMaxExprLen) {
+    why = "expression longer than " + std::to_string(kMaxExprLen) + " characters";
     return MU_E_ARG;
   }
   Parser ps;

@@ -44,3 +44,11 @@ def test_expression_errors_are_refused_with_their_place():
     many = " + ".join(f"p[{i}]" for i in range(29))
     st, msg = api.theory_check_expr(_th(many, n_par=29))
     assert st == A.MU_E_UNSUPPORTED and "28" in msg
+    # bounded parser and emitter: deep nesting, huge operation counts and
+    # overlong text are refused, not followed into the stack
+    for e, word in (("(" * 5000 + "p[1]" + ")" * 5000, "nesting"), ("-" * 5000 + "p[1]", "nesting"),
+                    (" + ".join(["p[1]"] * 5000), "operations"), ("p[1]" + " " * 70000, "longer")):
+        st, msg = api.theory_check_expr(_th(e))
+        assert st == A.MU_E_ARG and word in msg, (e[:20], st, msg)
+    st, _ = api.theory_check_expr(_th("(" * 150 + "p[1]" + ")" * 150))
+    assert st == A.MU_OK

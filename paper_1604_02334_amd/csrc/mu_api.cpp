@@ -463,6 +463,15 @@ static int tune_key(int shape, int mode, int cost, int split, int64_t work) {
   return (((shape * 4 + mode) * 2 + cost) * 2 + split) * 64 + lg;
 }
 
+// Smallest default range per wave: a wave's segment prologue and first
+// anchor cost about as much as 64 lane steps of the loop, so mid-sized
+// launches (the paper's Table 1 sizes: 1.4 M to 6.8 M bins) take ranges of
+// work / 512 bins, up to 4096, rather than one range per wave slot; large
+// launches are above the floor anyway, and small ones keep one bin per lane.
+static int64_t default_split_floor(int64_t work) {
+  return std::min<int64_t>(4096, std::max<int64_t>(kWave, work / 512));
+}
+
 int64_t mu_ctx::pick_split(int shape, int mode, int cost, int count_f64, int64_t work, int *anchor) const {
   *anchor = anchor_every;
   if (tile_bins > 0) return tile_bins;
@@ -473,11 +482,11 @@ int64_t mu_ctx::pick_split(int shape, int mode, int cost, int count_f64, int64_t
       return t.tile;
     }
   // one range per resident wave of the cost kernel (the same ranges for the
-  // cost and the gradient pass, so their costs agree bit for bit), at least
-  // one bin per lane
+  // cost and the gradient pass, so their costs agree bit for bit), but not
+  // below default_split_floor
   const int per_cu = eval_blocks_per_cu(kModeCost, cost, count_f64, shape);
   const int64_t cap = (int64_t)std::max(per_cu, 1) * (kBlock / kWave) * std::max(n_cu, 1);
-  return std::max<int64_t>(kWave, (work + cap - 1) / cap);
+  return std::max<int64_t>(default_split_floor(work), (work + cap - 1) / cap);
 }
 
 int64_t mu_ctx::pick_batch(int generic, int mode, int cost, int count_f64, int64_t work, int *anchor) const {
@@ -489,10 +498,11 @@ int64_t mu_ctx::pick_batch(int generic, int mode, int cost, int count_f64, int64
       *anchor = t.anchor;
       return t.tile;
     }
-  // one range per resident wave of the launch's kernel, at least one bin per lane
+  // one range per resident wave of the launch's kernel, but not below
+  // default_split_floor
   const int per_cu = eval_batch_blocks_per_cu(mode, cost, count_f64, generic);
   const int64_t cap = (int64_t)std::max(per_cu, 1) * (kBlock / kWave) * std::max(n_cu, 1);
-  return std::max<int64_t>(kWave, (work + cap - 1) / cap);
+  return std::max<int64_t>(default_split_floor(work), (work + cap - 1) / cap);
 }
 
 extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_histo, mu_data **out) {

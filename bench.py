@@ -62,6 +62,7 @@ VALU_PER_BIN_CHI2 = 14    # instructions per bin of the per-bin loop
 # 108 mul, 12 add per four bins, and 47 FP64 instructions per bin.
 FLOPS_PER_BIN_GRAD = 62
 VALU_PER_BIN_GRAD = 47
+VALU_PER_BIN_GRAD_EXPCOS = 30.25  # gradient loop of the exp * cos shape (C1, C3): 121 VALU per four bins
 BYTES_PER_BIN = 4         # one 32-bit count streamed per bin evaluation
 COUNTERS = os.path.join(ROOT, "profiles", "eval_grad_cost_kernel_c2_step_counters.md")
 KERNEL_SOURCES = ["paper_1604_02334_amd/csrc/mu_eval.hip", "paper_1604_02334_amd/csrc/mu_internal.h",
@@ -462,10 +463,43 @@ def _c3_stencils(api, ctx):
     S = torch.cat(St, 0).contiguous()
     sync = torch.cuda.synchronize
     out = {"vectors": nv, "bins": int(d.n_bins)}
+    import ctypes as C
+    from paper_1604_02334_amd import _abi as A
+    o = torch.empty(nv, dtype=torch.float64, device="cuda")
+    g = torch.empty((nv, npar), dtype=torch.float64, device="cuda")
+    pp, po, pg = (C.c_void_p(x.data_ptr()) for x in (P, o, g))
+
+    def direct():
+        A.lib().mu_chi2_grad(ctx.h, d.h, th.h, 0, pp, nv, A.MU_MEM_DEVICE, po, pg)
+
     with torch.cuda.stream(ctx.torch_stream):
         t = _wall_us(lambda: api.chi2_grad(ctx, d, th, P), 10, sync)
         out["grad_one_launch_us"] = round(t, 1)
         out["grad_one_launch_gbin_s"] = round(nv * d.n_bins / (t * 1e-6) / 1e9, 1)
+        # the C entry point with preallocated outputs, at the default and at
+        # the autotuned launch shape; kernel time from the library's events
+        out["grad_direct_us"] = round(_wall_us(direct, 10, sync), 1)
+        tg = api.autotune(ctx, d, th, P, grad=True)
+        out["grad_direct_tuned_us"] = round(_wall_us(direct, 10, sync), 1)
+        out["tuned_grad"] = tg[:2]
+        ctx.timing(True)
+        for _ in range(10):
+            direct()
+        sync()
+        ctx.timing(False)
+        n_g, ms_g = ctx.timing_read("grad")
+        n_m, ms_m = ctx.timing_read("merge")
+        out["tuned_kernels_us"] = {"grad": round(ms_g / max(n_g, 1) * 1e3, 2),
+                                   "merge": round(ms_m / max(n_m, 1) * 1e3, 2)}
+        bins = nv * d.n_bins
+        out["grad_kernel_gbin_s"] = round(bins / (out["tuned_kernels_us"]["grad"] * 1e-6) / 1e9, 1)
+        out["grad_direct_tuned_gbin_s"] = round(bins / (out["grad_direct_tuned_us"] * 1e-6) / 1e9, 1)
+        # VALU issue from the gradient loop's instruction count for this
+        # (exp * cos) shape, over the kernel and over the whole call
+        lane = bins * VALU_PER_BIN_GRAD_EXPCOS
+        out["valu_issue"] = {"instr_per_bin": VALU_PER_BIN_GRAD_EXPCOS,
+                             "kernel": round(lane / (out["tuned_kernels_us"]["grad"] * 1e-6) / 1e12 / PEAK_FP64_TOPS, 3),
+                             "call": round(lane / (out["grad_direct_tuned_us"] * 1e-6) / 1e12 / PEAK_FP64_TOPS, 3)}
         rows = [P[i:i + 1] for i in range(nv)]
 
         def separate():

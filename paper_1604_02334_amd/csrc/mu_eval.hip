@@ -847,11 +847,15 @@ __device__ __forceinline__ void eval_segment(const SegIn &S, double *slot) {
       if (k < n_terms && f < Sh::nf(ts, k)) {
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < kSlots; ++q)
+        for (int q = 0; q < kSlots; ++q) {
+          // slots the shape does not use are left out at compile time (fixed
+          // shapes), so the selection is a few compares rather than twelve
+          if (!(q / kMaxFT < n_terms && q % kMaxFT < Sh::nf(ts, q / kMaxFT))) continue;
           if (q == s) {
             a0 = R[kArg0 + 2 * q];
             a1 = R[kArg0 + 2 * q + 1];
           }
+        }
         const int kind = Sh::prim(ts, k, f);
         if (kind == MU_SE && w == 0) {
           earg = -a0 * h;

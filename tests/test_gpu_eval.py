@@ -422,6 +422,53 @@ def test_kernel_timing_records_each_launch(ctx):
     ctx.timing(False)
 
 
+def _tiny_set(n_bins):
+    th_d = synth.theory_exp_cos()
+    p = np.array([800.0, 4.0, 0.2, 0.7, 2.3, 0.4])
+    hs = [{"n_bins": n_bins, "dt": 0.01, "t0_bin": 0.0, "first": 0, "last": n_bins - 1, "map_row": 0}]
+    return th_d, hs, counts_for(th_d, hs, p, np.random.default_rng(77)), p
+
+
+@pytest.mark.parametrize("kind", ["chi2", "poisson"])
+def test_one_vector_matches_two_vector_launch(ctx, kind):
+    """At one fixed split, a one-vector call and a two-vector call evaluate
+    the first vector's bins as the same segments (a range may run on into the
+    second vector) and merge the same slots in the same order, so its cost,
+    per-histogram costs and gradient agree bit for bit. Calls alternate and
+    repeat; sets of one workgroup, of a ragged last workgroup and of many
+    workgroups; costs against the oracle at the parity bar."""
+    cfg, counts = c2()
+    th2, d2 = _mk(ctx, cfg["theory"], cfg["histos"], counts)
+    sets = [("c2", cfg["theory"], cfg["histos"], counts, cfg["p_true"], th2, d2)]
+    for n_bins in (300, 64 * 5 * 7 + 13):
+        th_d, hs, cnt, p = _tiny_set(n_bins)
+        th, d = _mk(ctx, th_d, hs, cnt)
+        sets.append((f"{n_bins} bins", th_d, hs, cnt, p, th, d))
+    old = ctx.tile
+    try:
+        for name, th_d, hs, cnt, p_true, th, d in sets:
+            for tile in (64, 4096):
+                _say("one vs two vectors", kind, name, "tile", tile)
+                ctx.tile = tile
+                for rep in range(3):
+                    p0 = perturbed(p_true, 1e-3, 300 + rep)
+                    p1 = perturbed(p_true, 1e-3, 400 + rep)
+                    c_one, h_one = api.chi2_eval(ctx, d, th, p0, kind, per_histo=True)
+                    c_two, h_two = api.chi2_eval(ctx, d, th, np.stack([p0, p1]), kind, per_histo=True)
+                    np.testing.assert_array_equal(c_one[0], c_two[0])
+                    np.testing.assert_array_equal(h_one[0], h_two[0])
+                    gc_one, g_one = api.chi2_grad(ctx, d, th, p0, kind)
+                    gc_two, g_two = api.chi2_grad(ctx, d, th, np.stack([p0, p1]), kind)
+                    np.testing.assert_array_equal(gc_one[0], gc_two[0])
+                    np.testing.assert_array_equal(g_one[0], g_two[0])
+                    if rep == 0 and tile == 4096:
+                        ref = model.cost(th_d, hs, cnt, p0, kind)
+                        assert abs(c_one[0] - ref) <= REL * abs(ref)
+                        assert abs(gc_one[0] - ref) <= REL * abs(ref)
+    finally:
+        ctx.tile = old
+
+
 @pytest.mark.parametrize("kind", ["chi2", "poisson"])
 def test_eval_grad_overlapped_matches_separate_calls(ctx, kind):
     """The combined gradient + cost call against the separate calls: the

@@ -356,8 +356,10 @@ mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_launches, dou
  * gradient when grad != 0) for several bins-per-wave values (powers of
  * two from 1024 to 65536, and the values that give 1, 2, 3, 4, 6 or 8
  * waves per resident wave slot) and anchor intervals 32 .. 256, keep
- * candidates whose costs agree with the first to 1e-12 relative, and
- * remember the fastest for later single-dataset launches of the same theory
+ * candidates whose costs agree with the first to 1e-12 relative, time the
+ * four fastest again (three interleaved rounds of ten launches; a candidate's
+ * best round counts), and remember the fastest for later single-dataset
+ * launches of the same theory
  * shape, mode, cost and size (to a power of two) while the tile size is 0.
  * Writes the choice and its time per launch in microseconds (any may be
  * NULL).  Leaves the explicit tile size and anchor interval unchanged. */
@@ -379,7 +381,8 @@ mu_status mu_autotune_set(mu_ctx *ctx, const mu_data *data, const mu_theory *th,
  * or cost and gradient when grad != 0) at several bins-per-wave values (1, 2,
  * 3, 4, 6 or 8 ranges per resident wave, powers of two from 1024 to 65536)
  * and anchor intervals 32 .. 256, keeps candidates whose costs agree with the
- * first to 1e-12 relative, and remembers the fastest for later batched
+ * first to 1e-12 relative, times the four fastest again as mu_autotune does,
+ * and remembers the fastest for later batched
  * launches of the same mode, cost and size (to a power of two) while the
  * tile size is 0.  Outputs as mu_autotune (any may be NULL). */
 mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *const *data, const mu_theory *const *th,

@@ -1511,6 +1511,41 @@ extern "C" mu_status mu_autotune_set(mu_ctx *ctx, const mu_data *data, const mu_
   return MU_OK;
 }
 
+// A tuning candidate that reproduced the reference costs, with its time per
+// launch (ms) from the first pass.
+struct TuneCand {
+  int64_t tile;
+  int anchor;
+  float ms;
+};
+
+// Final pass of both autotuners: the first pass times each candidate once,
+// in a fixed order while the clocks ramp, so candidates within a few percent
+// are not told apart. The fastest few are timed again in three interleaved
+// rounds of more launches each, and the one with the lowest time in any
+// round wins.
+template <typename TimeOne>
+static mu_status tune_final(std::vector<TuneCand> &passed, TimeOne &&time_one, int64_t &bt, int &ba, float &best) {
+  constexpr int kFinalists = 4, kRounds = 3, kReps = 10;
+  std::stable_sort(passed.begin(), passed.end(), [](const TuneCand &x, const TuneCand &y) { return x.ms < y.ms; });
+  if (passed.size() > (size_t)kFinalists) passed.resize(kFinalists);
+  for (TuneCand &c : passed) c.ms = 1e30f;
+  for (int r = 0; r < kRounds; ++r)
+    for (TuneCand &c : passed) {
+      float ms = 0.f;
+      const mu_status s = time_one(c.tile, c.anchor, kReps, ms);
+      if (s != MU_OK) return s;
+      c.ms = std::min(c.ms, ms);
+    }
+  for (const TuneCand &c : passed)
+    if (c.ms < best) {
+      best = c.ms;
+      bt = c.tile;
+      ba = c.anchor;
+    }
+  return MU_OK;
+}
+
 extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theory *th, mu_cost cost_kind,
                                  const double *params, int32_t n_vec, unsigned mem, int32_t grad,
                                  int32_t *best_tile, int32_t *best_anchor, double *best_us) {
@@ -1559,22 +1594,31 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
     for (int64_t w = kMinTile; w <= kMaxTile && w < work_all; w *= 2)
       if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
   }
+  // one candidate: two warm-up launches, then `reps` timed ones (ms per launch)
+  auto time_one = [&](int64_t tile, int anchor, int reps, float &ms) -> mu_status {
+    ctx->tile_bins = (int)tile;
+    ctx->anchor_every = anchor;
+    mu_status s = MU_OK;
+    for (int w = 0; w < 2 && s == MU_OK; ++w)
+      s = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
+    if (s != MU_OK) return s;
+    hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps && s == MU_OK; ++r)
+      s = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
+    hipEventRecord(e1, ctx->stream);
+    if (s != MU_OK) return s;
+    hipEventSynchronize(e1);
+    ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    return MU_OK;
+  };
+  std::vector<TuneCand> passed;
   for (size_t ci = 0; ci < cand.size() && st == MU_OK; ++ci) {
     const int64_t tile = cand[ci];
     for (int anchor : {32, 64, 128, 256}) {
-      ctx->tile_bins = (int)tile;
-      ctx->anchor_every = anchor;
-      for (int w = 0; w < 2 && st == MU_OK; ++w)
-        st = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
-      if (st != MU_OK) break;
-      hipEventRecord(e0, ctx->stream);
-      for (int r = 0; r < 5 && st == MU_OK; ++r)
-        st = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
-      hipEventRecord(e1, ctx->stream);
-      if (st != MU_OK) break;
-      hipEventSynchronize(e1);
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if ((st = time_one(tile, anchor, 5, ms)) != MU_OK) break;
       // every candidate must reproduce the first one's costs to rounding
       hipMemcpy(cur.data(), dc, n_vec * sizeof(double), hipMemcpyDeviceToHost);
       bool ok = true;
@@ -1586,13 +1630,10 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
           if (!(std::fabs(cur[v] - ref[v]) <= 1e-12 * std::fabs(ref[v])) && !(std::isnan(cur[v]) && std::isnan(ref[v])))
             ok = false;
       }
-      if (ok && ms < best) {
-        best = ms;
-        bt = tile;
-        ba = anchor;
-      }
+      if (ok) passed.push_back({tile, anchor, ms});
     }
   }
+  if (st == MU_OK) st = tune_final(passed, time_one, bt, ba, best);
   ctx->tile_bins = saved_tile;
   ctx->anchor_every = saved_anchor;
   hipEventDestroy(e0);
@@ -1608,7 +1649,7 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   remember_tuned(ctx, th, mode, cost_kind, work_all, (int)bt, ba);
   if (best_tile) *best_tile = (int32_t)bt;
   if (best_anchor) *best_anchor = ba;
-  if (best_us) *best_us = best / 5.0 * 1e3;
+  if (best_us) *best_us = best * 1e3;
   return MU_OK;
 }
 
@@ -1671,21 +1712,29 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
       if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
   }
   st = e == hipSuccess ? MU_OK : hip_fail(ctx, e, "hipMemcpyAsync(autotune)");
+  auto time_one = [&](int64_t tile, int anchor, int reps, float &ms) -> mu_status {
+    ctx->tile_bins = (int)tile;
+    ctx->anchor_every = anchor;
+    mu_status s = MU_OK;
+    for (int w = 0; w < 2 && s == MU_OK; ++w) s = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
+    if (s != MU_OK) return s;
+    hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps && s == MU_OK; ++r)
+      s = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
+    hipEventRecord(e1, ctx->stream);
+    if (s != MU_OK) return s;
+    hipEventSynchronize(e1);
+    ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    return MU_OK;
+  };
+  std::vector<TuneCand> passed;
   for (size_t ci = 0; ci < cand.size() && st == MU_OK; ++ci) {
     for (int anchor : {32, 64, 128, 256}) {
-      ctx->tile_bins = (int)std::min<int64_t>(cand[ci], kMaxSplit);
-      ctx->anchor_every = anchor;
-      for (int w = 0; w < 2 && st == MU_OK; ++w)
-        st = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
-      if (st != MU_OK) break;
-      hipEventRecord(e0, ctx->stream);
-      for (int r = 0; r < 5 && st == MU_OK; ++r)
-        st = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
-      hipEventRecord(e1, ctx->stream);
-      if (st != MU_OK) break;
-      hipEventSynchronize(e1);
+      const int64_t tile = std::min<int64_t>(cand[ci], kMaxSplit);
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if ((st = time_one(tile, anchor, 5, ms)) != MU_OK) break;
       // every candidate must reproduce the first one's costs to rounding
       hipMemcpy(cur.data(), dc, n_jobs * sizeof(double), hipMemcpyDeviceToHost);
       bool ok = true;
@@ -1697,13 +1746,10 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
           if (!(std::fabs(cur[j] - ref[j]) <= 1e-12 * std::fabs(ref[j])) && !(std::isnan(cur[j]) && std::isnan(ref[j])))
             ok = false;
       }
-      if (ok && ms < best) {
-        best = ms;
-        bt = ctx->tile_bins;
-        ba = anchor;
-      }
+      if (ok) passed.push_back({tile, anchor, ms});
     }
   }
+  if (st == MU_OK) st = tune_final(passed, time_one, bt, ba, best);
   ctx->tile_bins = saved_tile;
   ctx->anchor_every = saved_anchor;
   hipEventDestroy(e0);
@@ -1720,7 +1766,7 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
                                    (int)bt, ba);
   if (best_tile) *best_tile = (int32_t)bt;
   if (best_anchor) *best_anchor = ba;
-  if (best_us) *best_us = best / 5.0 * 1e3;
+  if (best_us) *best_us = best * 1e3;
   return MU_OK;
 }
 

@@ -405,8 +405,9 @@ __device__ __forceinline__ double value_grad(int kind, double t, double a0, doub
 }
 
 // Per-bin cost term (Eq. 2 / Eq. 3) and its derivative in N.
-// 1/v for v >= 1: hardware reciprocal refined by one Newton step (< 1 ulp +
-// rounding).
+// 1/v for normal v whose reciprocal is normal (v >= 1 for the counts,
+// 2^-1000 < v < 2^1000 for the likelihood's expected counts): hardware
+// reciprocal refined by one Newton step (< 1 ulp + rounding).
 __device__ __forceinline__ double recip(double v) {
   double iv = __builtin_amdgcn_rcp(v);
   return fma(iv, fma(-v, iv, 1.0), iv);
@@ -479,7 +480,16 @@ __device__ __forceinline__ double cost_term(double d, double N, double iv_int, d
     return diff * diff * iv;
   } else {
     if (d > 0.0) {
-      const double q = d / N;
+      // q = d / N as d times the refined hardware reciprocal (within about
+      // 2 ulp; the division's scaling and fix-up steps cost twice as many
+      // instructions). A wave-uniform test sends waves with any N outside
+      // [2^-1000, 2^1000], or not positive, to the division, which handles
+      // every range.
+      double q;
+      if (__builtin_amdgcn_ballot_w64(!(N > 0x1p-1000 && N < 0x1p1000)) == 0)
+        q = d * recip(N);
+      else
+        q = d / N;
       if (WANT_DN) dN = 2.0 * (1.0 - q);
       if (!(N > 0.0)) return (N <= 0.0) ? INFINITY : N;  // NaN stays NaN
       return 2.0 * ((N - d) + d * log_ratio(q));

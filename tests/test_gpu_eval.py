@@ -231,6 +231,30 @@ def test_edge_cases(ctx):
     assert api.chi2_eval(ctx, d2, th2, neg, "poisson")[0] == math.inf
 
 
+def test_likelihood_extreme_expected_counts(ctx):
+    """The likelihood's ratio d / N is d times a refined reciprocal while every
+    N of a wave lies in [2^-1000, 2^1000], else the division. Expected counts
+    from 4e-302 to 1e-299 and from 4e298 to 1e301 (histograms whose waves
+    straddle 2^-1000 and 2^1000) take both paths; costs and gradients against
+    the oracle at the parity bar."""
+    _say("likelihood extreme N")
+    th_d = synth.theory_exp_cos()
+    hs = [{"n_bins": 6000, "dt": 0.002, "t0_bin": 0.0, "first": 0, "last": 5999, "map_row": 0}]
+    rng = np.random.default_rng(5)
+    cnt = [(rng.poisson(3.0, 6000) + 1).astype(np.float64)]
+    th, d = _mk(ctx, th_d, hs, cnt)
+    for n0 in (1e-299, 1e301):
+        p = np.array([n0, 0.0, 0.2, 0.7, 2.3, 0.4])
+        ref = model.cost(th_d, hs, cnt, p, "poisson")
+        got = api.chi2_eval(ctx, d, th, p, "poisson")[0]
+        assert math.isfinite(ref) and abs(got - ref) <= REL * abs(ref), (n0, got, ref)
+        c, g = api.chi2_grad(ctx, d, th, p, "poisson")
+        assert abs(c[0] - ref) <= REL * abs(ref)
+        gref = model.grad(th_d, hs, cnt, p, "poisson")
+        scale = model.grad_abs_scale(th_d, hs, cnt, p, "poisson")
+        assert np.all(np.abs(g[0] - gref) <= REL * scale)
+
+
 def test_primitive_coverage(ctx):
     """ge with a literal and a free beta, stg, sg and the function-array route."""
     _say("primitives")

@@ -1491,7 +1491,7 @@ __global__ __launch_bounds__(kBlock, 4) void eval_grad_cost_kernel(LaunchArgs g,
   if ((int)blockIdx.x < n_grad_blocks)
     eval_units<COST, kModeGrad, CT, Sh, TAB>(g, blockIdx.x, inv_tab);
   else
-    eval_units<COST, kModeCost, CT, Sh, TAB>(c, blockIdx.x - n_grad_blocks, inv_tab);
+    eval_units<COST, kModeCost, CT, Sh, TAB, kPrefetchStream>(c, blockIdx.x - n_grad_blocks, inv_tab);
 }
 
 // One workgroup per job: fixed-order merge of the job's slots.  It runs as

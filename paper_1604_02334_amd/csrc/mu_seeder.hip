@@ -9,7 +9,7 @@
 // Hoermann's transformed rejection (PTRS, 1993) above.
 //
 // Network: 1024-512-256-128-8 perceptron with ReLU.  GEMMs use the
-// 16x16x16 BF16 matrix-core instruction with FP32 accumulation; activations and
+// 16x16x32 BF16 matrix-core instruction with FP32 accumulation; activations and
 // gradients are rounded to BF16 where they feed a GEMM and kept in FP32
 // elsewhere (bias, ReLU mask, bias gradient, Adam master weights).
 
@@ -87,6 +87,25 @@ __device__ void draw_theta(unsigned long long seed, unsigned long long idx, doub
   th[5] = u[5] * kTwoPi;
 }
 
+// ln k! for the rejection test: the log-gamma function below k = 10, else
+// Stirling's series for ln Gamma(k + 1) to the z^-5 term (its first omitted
+// term is below 1 / (1680 z^7) = 6e-11 at z = 11), as the method itself
+// prescribes; the full log-gamma costs several times as much and every lane
+// of a wave runs it whenever one lane takes the slow test.
+// out of line: the log-gamma's many constants would otherwise raise the
+// generator's register count for a branch that rarely runs
+__device__ __attribute__((noinline)) double x_lgamma(double x) { return lgamma(x); }
+__device__ __forceinline__ double log_factorial(double k) {
+  const double z = fmax(k, 10.0) + 1.0, iz = 1.0 / z, iz2 = iz * iz;
+  double lf = (z - 0.5) * log(z) - z + 0.91893853320467274178 + iz * (1.0 / 12.0 - iz2 * (1.0 / 360.0 - iz2 * (1.0 / 1260.0)));
+  // a wave-uniform test, so the log-gamma runs only in waves that need it
+  if (__builtin_amdgcn_ballot_w64(k < 10.0) != 0) {
+    asm volatile("");
+    if (k < 10.0) lf = x_lgamma(k + 1.0);
+  }
+  return lf;
+}
+
 // One Poisson draw with mean mu from the counter stream (idx, bin, it).
 __device__ double poisson(double mu, unsigned long long seed, unsigned long long idx, unsigned bin) {
   const unsigned k0 = (unsigned)seed, k1 = (unsigned)(seed >> 32);
@@ -109,6 +128,7 @@ __device__ double poisson(double mu, unsigned long long seed, unsigned long long
   const double a = -0.059 + 0.02483 * b;
   const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
   const double vr = 0.9277 - 3.6224 / (b - 2.0);
+  const double log_invalpha = log(invalpha);
   for (unsigned it = 0; it < 64; ++it) {
     const U4 r = philox(U4{(unsigned)idx, (unsigned)(idx >> 32), bin, it + 1u}, k0, k1);
     const double us_pair[2][2] = {{u01(r.x), u01(r.y)}, {u01(r.z), u01(r.w)}};
@@ -118,7 +138,7 @@ __device__ double poisson(double mu, unsigned long long seed, unsigned long long
       const double k = floor((2.0 * a / us + b) * U + mu + 0.43);
       if (us >= 0.07 && V <= vr) return k;
       if (k < 0.0 || (us < 0.013 && V > us)) continue;
-      if (log(V) + log(invalpha) - log(a / (us * us) + b) <= -mu + k * loglam - lgamma(k + 1.0)) return k;
+      if (log(V) + log_invalpha - log(a / (us * us) + b) <= -mu + k * loglam - log_factorial(k)) return k;
     }
   }
   return floor(mu + 0.5);  // not reached in practice (acceptance > 0.9 per try)
@@ -137,15 +157,29 @@ __global__ __launch_bounds__(256) void gen_kernel(unsigned long long seed, unsig
   draw_theta(seed, idx, th);
   const double w = kTwoPi * th[4];
   const int nb = fine ? kFine : kCoarse, sub = fine ? 1 : kRebin;
-  // a rebinned bin's fine bins: the first evaluated directly, the others by
-  // one fine step of each factor (geometric decays, rotation)
+  // a rebinned bin's fine bins: the first from the bin's start state, the
+  // others by one fine step of each factor (geometric decays, rotation); the
+  // thread's first bin starts from a direct evaluation, each later one
+  // (blockDim.x bins on) from one step of that stride
   const double r1 = exp(-kDtFine / kTau), r2 = exp(-th[3] * kDtFine);
   double sw, cw;
   sincos(w * kDtFine, &sw, &cw);
+  const double t_first = (double)((int)threadIdx.x * sub) * kDtFine;
+  const double t_stride = (double)((int)blockDim.x * sub) * kDtFine;
+  double E1 = exp(-t_first / kTau), E2 = exp(-th[3] * t_first), SN, CS;
+  sincos(w * t_first + th[5], &SN, &CS);
+  const double R1 = exp(-t_stride / kTau), R2 = exp(-th[3] * t_stride);
+  double SW, CW;
+  sincos(w * t_stride, &SW, &CW);
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    const double t0 = (double)(b * sub) * kDtFine;
-    double e1 = exp(-t0 / kTau), e2 = exp(-th[3] * t0), sn, cs;
-    sincos(w * t0 + th[5], &sn, &cs);
+    double e1 = E1, e2 = E2, sn = SN, cs = CS;
+    {
+      E1 *= R1;
+      E2 *= R2;
+      const double c2 = CS * CW - SN * SW;
+      SN = SN * CW + CS * SW;
+      CS = c2;
+    }
     double mu = 0.0;
     for (int q = 0; q < sub; ++q) {
       mu += th[0] * e1 * (1.0 + th[2] * e2 * cs) + th[1];

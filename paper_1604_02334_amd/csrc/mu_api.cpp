@@ -1568,10 +1568,17 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(autotune)");
   e = hipMemcpyAsync(buf, params, n_p * sizeof(double),
                      mem == MU_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(buf);
+    return hip_fail(ctx, e, "hipMemcpyAsync(autotune)");
+  }
   double *dc = buf + n_p, *dg = grad ? dc + n_vec : nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(buf);
+    return hip_fail(ctx, e, "hipEventCreate(autotune)");
+  }
   const int saved_tile = ctx->tile_bins, saved_anchor = ctx->anchor_every;
   std::vector<double> ref(n_vec), cur(n_vec);
   bool have_ref = false;
@@ -1602,14 +1609,15 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
     for (int w = 0; w < 2 && s == MU_OK; ++w)
       s = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
     if (s != MU_OK) return s;
-    hipEventRecord(e0, ctx->stream);
-    for (int r = 0; r < reps && s == MU_OK; ++r)
+    hipError_t he = hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps && s == MU_OK && he == hipSuccess; ++r)
       s = eval_uniform(ctx, d, th, cost_kind, buf, n_vec, MU_MEM_DEVICE, dc, nullptr, dg, nullptr, mode);
-    hipEventRecord(e1, ctx->stream);
     if (s != MU_OK) return s;
-    hipEventSynchronize(e1);
     ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) return hip_fail(ctx, he, "autotune timing events");
     ms /= (float)reps;
     return MU_OK;
   };
@@ -1620,7 +1628,11 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
       float ms = 0.f;
       if ((st = time_one(tile, anchor, 5, ms)) != MU_OK) break;
       // every candidate must reproduce the first one's costs to rounding
-      hipMemcpy(cur.data(), dc, n_vec * sizeof(double), hipMemcpyDeviceToHost);
+      const hipError_t ce = hipMemcpy(cur.data(), dc, n_vec * sizeof(double), hipMemcpyDeviceToHost);
+      if (ce != hipSuccess) {
+        st = hip_fail(ctx, ce, "hipMemcpy(autotune costs)");
+        break;
+      }
       bool ok = true;
       if (!have_ref) {
         ref = cur;
@@ -1636,10 +1648,10 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
   if (st == MU_OK) st = tune_final(passed, time_one, bt, ba, best);
   ctx->tile_bins = saved_tile;
   ctx->anchor_every = saved_anchor;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamSynchronize(ctx->stream);
-  hipFree(buf);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(ctx->stream);  // before freeing what the launches use
+  (void)hipFree(buf);
   if (st != MU_OK) return st;
   if (bt == 0) {
     set_err(ctx, "no tuning candidate ran");
@@ -1666,7 +1678,7 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
     set_err(ctx, "autotune_batch needs n_jobs >= 1, data, theories, parameters, ld >= 1, a memory kind and a cost kind");
     return MU_E_ARG;
   }
-  mu_status st;
+  mu_status st = MU_OK;
   for (int j = 0; j < n_jobs; ++j) {
     if ((st = check_pair(ctx, data[j], th[j])) != MU_OK) return st;
     if (th[j]->h.n_par > ld || data[j]->f64 != data[0]->f64) {
@@ -1690,10 +1702,17 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(autotune)");
   e = hipMemcpyAsync(buf, params, n_p * sizeof(double),
                      mem == MU_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(buf);
+    return hip_fail(ctx, e, "hipMemcpyAsync(autotune)");
+  }
   double *dc = buf + n_p, *dg = grad ? dc + n_jobs : nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(buf);
+    return hip_fail(ctx, e, "hipEventCreate(autotune)");
+  }
   const int saved_tile = ctx->tile_bins, saved_anchor = ctx->anchor_every;
   std::vector<double> ref(n_jobs), cur(n_jobs);
   bool have_ref = false;
@@ -1711,21 +1730,21 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
     for (int64_t w = kMinTile; w <= kMaxTile && w < total[lead]; w *= 2)
       if (std::find(cand.begin(), cand.end(), w) == cand.end()) cand.push_back(w);
   }
-  st = e == hipSuccess ? MU_OK : hip_fail(ctx, e, "hipMemcpyAsync(autotune)");
   auto time_one = [&](int64_t tile, int anchor, int reps, float &ms) -> mu_status {
     ctx->tile_bins = (int)tile;
     ctx->anchor_every = anchor;
     mu_status s = MU_OK;
     for (int w = 0; w < 2 && s == MU_OK; ++w) s = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
     if (s != MU_OK) return s;
-    hipEventRecord(e0, ctx->stream);
-    for (int r = 0; r < reps && s == MU_OK; ++r)
+    hipError_t he = hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps && s == MU_OK && he == hipSuccess; ++r)
       s = run_batch(ctx, n_jobs, data, th, cost_kind, ld, buf, MU_MEM_DEVICE, dc, dg);
-    hipEventRecord(e1, ctx->stream);
     if (s != MU_OK) return s;
-    hipEventSynchronize(e1);
     ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) return hip_fail(ctx, he, "autotune timing events");
     ms /= (float)reps;
     return MU_OK;
   };
@@ -1736,7 +1755,11 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
       float ms = 0.f;
       if ((st = time_one(tile, anchor, 5, ms)) != MU_OK) break;
       // every candidate must reproduce the first one's costs to rounding
-      hipMemcpy(cur.data(), dc, n_jobs * sizeof(double), hipMemcpyDeviceToHost);
+      const hipError_t ce = hipMemcpy(cur.data(), dc, n_jobs * sizeof(double), hipMemcpyDeviceToHost);
+      if (ce != hipSuccess) {
+        st = hip_fail(ctx, ce, "hipMemcpy(autotune costs)");
+        break;
+      }
       bool ok = true;
       if (!have_ref) {
         ref = cur;
@@ -1752,10 +1775,10 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
   if (st == MU_OK) st = tune_final(passed, time_one, bt, ba, best);
   ctx->tile_bins = saved_tile;
   ctx->anchor_every = saved_anchor;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamSynchronize(ctx->stream);
-  hipFree(buf);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(ctx->stream);  // before freeing what the launches use
+  (void)hipFree(buf);
   if (st != MU_OK) return st;
   if (bt == 0) {
     set_err(ctx, "no tuning candidate ran");

@@ -51,8 +51,8 @@ mu_status DevBuf::ensure(mu_ctx *ctx, size_t bytes, bool zero) {
     return MU_E_UNSUPPORTED;
   }
   if (ptr) {
-    hipStreamSynchronize(ctx->stream);
-    hipFree(ptr);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ptr);
     ptr = nullptr;
     cap = 0;
   }
@@ -73,7 +73,7 @@ mu_status DevBuf::ensure(mu_ctx *ctx, size_t bytes, bool zero) {
 }
 
 void DevBuf::release() {
-  if (ptr && !fixed) hipFree(ptr);
+  if (ptr && !fixed) (void)hipFree(ptr);
   ptr = nullptr;
   cap = 0;
 }
@@ -81,8 +81,8 @@ void DevBuf::release() {
 mu_status HostBuf::ensure(mu_ctx *ctx, size_t bytes) {
   if (bytes <= cap) return MU_OK;
   if (ptr) {
-    hipStreamSynchronize(ctx->stream);
-    hipHostFree(ptr);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipHostFree(ptr);
     ptr = nullptr;
     cap = 0;
   }
@@ -99,7 +99,7 @@ mu_status HostBuf::ensure(mu_ctx *ctx, size_t bytes) {
 }
 
 void HostBuf::release() {
-  if (ptr) hipHostFree(ptr);
+  if (ptr) (void)hipHostFree(ptr);
   ptr = nullptr;
   cap = 0;
 }
@@ -161,7 +161,7 @@ extern "C" mu_status mu_ctx_create(int device, void *hip_stream, unsigned flags,
     c->own_stream = true;
   }
   if (hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming) != hipSuccess) {
-    if (c->own_stream) hipStreamDestroy(c->stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return MU_E_DEVICE;
   }
@@ -173,9 +173,9 @@ extern "C" mu_status mu_ctx_create(int device, void *hip_stream, unsigned flags,
     hipError_t e = hipMalloc(&c->d_inv, inv.size() * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(c->d_inv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-      if (c->d_inv) hipFree(c->d_inv);
-      hipEventDestroy(c->staging_free);
-      if (c->own_stream) hipStreamDestroy(c->stream);
+      if (c->d_inv) (void)hipFree(c->d_inv);
+      (void)hipEventDestroy(c->staging_free);
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
       delete c;
       return MU_E_DEVICE;
     }
@@ -190,15 +190,15 @@ extern "C" mu_status mu_ctx_destroy(mu_ctx *ctx) {
     set_err(ctx, "context still owns %d live handles", ctx->children);
     return MU_E_STATE;
   }
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   ctx->release_all();
-  if (ctx->d_inv) hipFree(ctx->d_inv);
-  if (ctx->staging_free) hipEventDestroy(ctx->staging_free);
-  for (hipEvent_t ev : ctx->ev_pool) hipEventDestroy(ev);
+  if (ctx->d_inv) (void)hipFree(ctx->d_inv);
+  if (ctx->staging_free) (void)hipEventDestroy(ctx->staging_free);
+  for (hipEvent_t ev : ctx->ev_pool) (void)hipEventDestroy(ev);
   for (auto &m : ctx->rtc)
-    if (m.mod) hipModuleUnload(m.mod);
-  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    if (m.mod) (void)hipModuleUnload(m.mod);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return MU_OK;
 }
@@ -232,7 +232,7 @@ int mu_ctx::time_begin(int kind, hipStream_t s) {
 }
 
 void mu_ctx::time_end(int idx, hipStream_t s) {
-  if (idx >= 0) hipEventRecord(timed[idx].b, s);
+  if (idx >= 0) (void)hipEventRecord(timed[idx].b, s);  // timing only
 }
 
 extern "C" mu_status mu_ctx_timing(mu_ctx *ctx, int32_t enable) {
@@ -248,7 +248,7 @@ extern "C" mu_status mu_ctx_timing_read(mu_ctx *ctx, int32_t kind, int32_t *n_la
     set_err(ctx, "mu_ctx_timing_read: unknown kind %d or NULL output", kind);
     return MU_E_ARG;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   int32_t n = 0;
   double tot = 0.0;
   for (const auto &t : ctx->timed) {
@@ -270,7 +270,7 @@ extern "C" const char *mu_ctx_last_error(const mu_ctx *ctx) { return ctx ? ctx->
 
 extern "C" mu_status mu_ctx_synchronize(mu_ctx *ctx) {
   if (!ctx) return MU_E_ARG;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   hipError_t e = hipStreamSynchronize(ctx->stream);
   return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "hipStreamSynchronize");
 }
@@ -435,7 +435,7 @@ mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out, int *lds)
   hipError_t e = hipMalloc(&p.d, buf.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(p.d, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    if (p.d) hipFree(p.d);
+    if (p.d) (void)hipFree(p.d);
     return hip_fail(ctx, e, "gradient merge plan");
   }
   plans.push_back(p);
@@ -446,11 +446,11 @@ mu_status mu_data::grad_plan(const mu_theory *th, const int32_t **out, int *lds)
 
 void mu_data::free_dev() {
   for (Plan &p : plans)
-    if (p.d) hipFree(p.d);
+    if (p.d) (void)hipFree(p.d);
   plans.clear();
-  if (counts) hipFree(counts);
+  if (counts) (void)hipFree(counts);
   counts = nullptr;
-  if (d_hh) hipFree(d_hh);
+  if (d_hh) (void)hipFree(d_hh);
   d_hh = nullptr;
 }
 
@@ -515,7 +515,7 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
     set_err(ctx, "%s", why.c_str());
     return st;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   mu_data *d = new mu_data();
   d->ctx = ctx;
   d->n_histo = n_histo;
@@ -578,8 +578,8 @@ extern "C" mu_status mu_data_create(mu_ctx *ctx, const mu_histo *h, int32_t n_hi
 
 extern "C" mu_status mu_data_destroy(mu_data *d) {
   if (!d) return MU_E_ARG;
-  hipSetDevice(d->ctx->device);
-  hipStreamSynchronize(d->ctx->stream);
+  (void)hipSetDevice(d->ctx->device);
+  (void)hipStreamSynchronize(d->ctx->stream);
   d->free_dev();
   d->ctx->children--;
   delete d;
@@ -758,7 +758,7 @@ extern "C" mu_status mu_theory_create(mu_ctx *ctx, const mu_theory_desc *d, mu_t
     set_err(ctx, "%s", why.c_str());
     return s;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   static std::atomic<uint64_t> next_id{1};
   mu_theory *th = new mu_theory();
   th->ctx = ctx;
@@ -827,10 +827,10 @@ extern "C" mu_status mu_theory_create(mu_ctx *ctx, const mu_theory_desc *d, mu_t
 }
 
 void mu_theory::free_dev() {
-  if (d_map) hipFree(d_map);
-  if (d_F) hipFree(d_F);
-  if (d_f0) hipFree(d_f0);
-  if (d_th) hipFree(d_th);
+  if (d_map) (void)hipFree(d_map);
+  if (d_F) (void)hipFree(d_F);
+  if (d_f0) (void)hipFree(d_f0);
+  if (d_th) (void)hipFree(d_th);
   d_map = nullptr;
   d_F = d_f0 = nullptr;
   d_th = nullptr;
@@ -838,8 +838,8 @@ void mu_theory::free_dev() {
 
 extern "C" mu_status mu_theory_destroy(mu_theory *th) {
   if (!th) return MU_E_ARG;
-  hipSetDevice(th->ctx->device);
-  hipStreamSynchronize(th->ctx->stream);
+  (void)hipSetDevice(th->ctx->device);
+  (void)hipStreamSynchronize(th->ctx->stream);
   th->free_dev();
   th->ctx->children--;
   delete th;
@@ -1003,7 +1003,7 @@ mu_status eval_uniform(mu_ctx *ctx, mu_data *d, const mu_theory *th, int cost_ki
                        int mode) {
   mu_status st = check_eval_args(ctx, cost_kind, mem, n_vec, params);
   if (st != MU_OK) return st;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   const int n_par = th->h.n_par;
   const size_t n_p = (size_t)n_vec * n_par;
   const size_t n_h = histo ? (size_t)n_vec * d->n_histo : 0;
@@ -1055,7 +1055,7 @@ mu_status eval_grad_and_costs(mu_ctx *ctx, mu_data *d, const mu_theory *th, int 
   mu_status st = check_eval_args(ctx, cost_kind, mem, n_grad, pg);
   if (st == MU_OK) st = check_eval_args(ctx, cost_kind, mem, n_cost, pc);
   if (st != MU_OK) return st;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   const int n_par = th->h.n_par;
   const size_t n_pg = (size_t)n_grad * n_par, n_pc = (size_t)n_cost * n_par;
   const size_t n_out = (size_t)n_grad + (size_t)n_grad * n_par + (size_t)n_cost;
@@ -1167,7 +1167,7 @@ extern "C" mu_status mu_chi2_eval_static(mu_ctx *ctx, const mu_data *data, const
     set_err(ctx, "the allocation-free slots of device %d were not found (hipGetSymbolAddress failed)", ctx->device);
     return MU_E_DEVICE;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   // the same launch as mu_chi2_eval with device memory, its slots in the
   // device's static array (a fixed buffer: a launch needing more slots is
   // refused before anything is enqueued)
@@ -1255,7 +1255,7 @@ extern "C" mu_status mu_chi2_batch(mu_ctx *ctx, int32_t n_jobs, const mu_data *c
       return MU_E_UNSUPPORTED;
     }
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   return run_batch(ctx, n_jobs, data, th, cost_kind, ld, params, mem, cost, grad);
 }
 
@@ -1557,7 +1557,7 @@ extern "C" mu_status mu_autotune(mu_ctx *ctx, const mu_data *data, const mu_theo
     set_err(ctx, "autotune needs parameters, n_vec >= 1, a memory kind and a cost kind");
     return MU_E_ARG;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   mu_data *d = const_cast<mu_data *>(data);
   const int n_par = th->h.n_par;
   const int mode = grad ? kModeGrad : kModeCost;
@@ -1686,7 +1686,7 @@ extern "C" mu_status mu_autotune_batch(mu_ctx *ctx, int32_t n_jobs, const mu_dat
       return MU_E_ARG;
     }
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   const int mode = grad ? kModeGrad : kModeCost;
   const int f64 = data[0]->f64;
   // the two launch groups of run_batch and their sizes

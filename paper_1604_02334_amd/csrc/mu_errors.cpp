@@ -218,7 +218,7 @@ extern "C" mu_status mu_hesse(mu_ctx *ctx, const mu_data *data, const mu_theory 
       set_err(ctx, "parameter %d is not finite", k);
       return MU_E_ARG;
     }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   std::vector<int> free;
   for (int k = 0; k < n_par; ++k)
     if (!(fixed && fixed[k])) free.push_back(k);

@@ -438,7 +438,7 @@ extern "C" mu_status mu_theory_create_expr(mu_ctx *ctx, const mu_expr_theory_des
     set_err(ctx, "%s", why.c_str());
     return st;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   // one module per distinct source on this context
   hipFunction_t fn = nullptr;
   for (const auto &m : ctx->rtc)
@@ -456,7 +456,7 @@ extern "C" mu_status mu_theory_create_expr(mu_ctx *ctx, const mu_expr_theory_des
     hipError_t e = hipModuleLoadData(&m.mod, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&m.fn, m.mod, "mu_rtc_kernel");
     if (e != hipSuccess) {
-      if (m.mod) hipModuleUnload(m.mod);
+      if (m.mod) (void)hipModuleUnload(m.mod);
       return hip_fail(ctx, e, "loading the compiled theory");
     }
     ctx->rtc.push_back(m);

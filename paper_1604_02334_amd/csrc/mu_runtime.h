@@ -105,10 +105,10 @@ struct mu_ctx {
 
   // Wait until the last upload from `staging` has been consumed.
   void wait_staging() {
-    if (staging_free) hipEventSynchronize(staging_free);
+    if (staging_free) (void)hipEventSynchronize(staging_free);
   }
   void mark_staging() {
-    if (staging_free) hipEventRecord(staging_free, stream);
+    if (staging_free) (void)hipEventRecord(staging_free, stream);
   }
 };
 

@@ -674,27 +674,27 @@ struct mu_seeder {
 
 void mu_seeder::free_acts() {
   for (int l = 0; l < kSeedLayers; ++l) {
-    hipFree(X[l]);
-    hipFree(Z[l]);
-    hipFree(dZ[l]);
-    hipFree(G[l]);
+    (void)hipFree(X[l]);
+    (void)hipFree(Z[l]);
+    (void)hipFree(dZ[l]);
+    (void)hipFree(G[l]);
     X[l] = nullptr;
     Z[l] = dZ[l] = nullptr;
     G[l] = nullptr;
   }
-  hipFree(T);
-  hipFree(loss);
-  hipFree(counts);
-  hipFree(partial);
-  hipFree(theta);
-  hipFree(scale);
-  hipFree(mf);
-  hipFree(ml);
-  hipFree(start);
-  hipFree(ok);
-  hipFree(srcs);
-  hipFree(ws);
-  hipFree(bpart);
+  (void)hipFree(T);
+  (void)hipFree(loss);
+  (void)hipFree(counts);
+  (void)hipFree(partial);
+  (void)hipFree(theta);
+  (void)hipFree(scale);
+  (void)hipFree(mf);
+  (void)hipFree(ml);
+  (void)hipFree(start);
+  (void)hipFree(ok);
+  (void)hipFree(srcs);
+  (void)hipFree(ws);
+  (void)hipFree(bpart);
   ws = nullptr;
   bpart = nullptr;
   ws_floats = 0;
@@ -707,18 +707,18 @@ void mu_seeder::free_acts() {
 
 void mu_seeder::free_all() {
   free_acts();
-  hipFree(params);
-  hipFree(grads);
-  hipFree(m);
-  hipFree(v);
-  hipFree(wbf);
+  (void)hipFree(params);
+  (void)hipFree(grads);
+  (void)hipFree(m);
+  (void)hipFree(v);
+  (void)hipFree(wbf);
   params = grads = m = v = nullptr;
   wbf = nullptr;
 }
 
 mu_status mu_seeder::ensure(int B) {
   if (B <= cap) return MU_OK;
-  hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   free_acts();
   hipError_t e = hipSuccess;
   auto al = [&](void **p, size_t bytes) {
@@ -910,7 +910,7 @@ extern "C" mu_status mu_seeder_create(mu_ctx *ctx, const float *init_params, mu_
       set_err(ctx, "initial seeder parameter %zu is not finite", i);
       return MU_E_ARG;
     }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   mu_seeder *S = new mu_seeder();
   S->ctx = ctx;
   S->n_params = n;
@@ -946,8 +946,8 @@ extern "C" mu_status mu_seeder_create(mu_ctx *ctx, const float *init_params, mu_
 
 extern "C" mu_status mu_seeder_destroy(mu_seeder *S) {
   if (!S) return MU_E_ARG;
-  hipSetDevice(S->ctx->device);
-  hipStreamSynchronize(S->ctx->stream);
+  (void)hipSetDevice(S->ctx->device);
+  (void)hipStreamSynchronize(S->ctx->stream);
   S->free_all();
   S->ctx->children--;
   delete S;
@@ -976,7 +976,7 @@ extern "C" mu_status mu_gen_histos(mu_ctx *ctx, uint64_t seed, uint64_t first, i
     if (ctx) set_err(ctx, "mu_gen_histos needs n >= 1, a memory kind and at least one output");
     return MU_E_ARG;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   float *dc = counts;
   double *dt = theta, *dm = mu;
   void *tmp = nullptr;
@@ -998,7 +998,7 @@ extern "C" mu_status mu_gen_histos(mu_ctx *ctx, uint64_t seed, uint64_t first, i
     if (e == hipSuccess && theta) e = hipMemcpyAsync(theta, dt, bt, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess && mu) e = hipMemcpyAsync(mu, dm, bm, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    hipFree(tmp);
+    (void)hipFree(tmp);
   }
   return e == hipSuccess ? MU_OK : hip_fail(ctx, e, "generator");
 }
@@ -1006,7 +1006,7 @@ extern "C" mu_status mu_gen_histos(mu_ctx *ctx, uint64_t seed, uint64_t first, i
 extern "C" mu_status mu_seeder_forward(mu_ctx *ctx, mu_seeder *S, const uint16_t *x_bf16, int32_t B, unsigned mem,
                                        float *y) {
   if (!ctx || !S || !x_bf16 || !y || B < 1 || !mem_ok(mem) || S->ctx != ctx) return MU_E_ARG;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   mu_status st = S->ensure(B);
   if (st != MU_OK) return st;
   if ((st = copy_in(ctx, S->X[0], x_bf16, (size_t)B * kCoarse * 2, mem)) != MU_OK) return st;
@@ -1022,7 +1022,7 @@ extern "C" mu_status mu_seeder_layer(mu_ctx *ctx, const mu_seeder *S, int32_t la
     set_err(ctx, "mu_seeder_layer: the last forward (backward) pass held %d (%d) samples", S->fwd_B, S->bwd_B);
     return MU_E_STATE;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   const size_t K = kDims[layer], N = kDims[layer + 1];
   mu_status st = MU_OK;
   if (x_in) st = copy_out(ctx, x_in, S->X[layer], (size_t)B * K * 2, MU_MEM_HOST);
@@ -1035,7 +1035,7 @@ extern "C" mu_status mu_seeder_layer(mu_ctx *ctx, const mu_seeder *S, int32_t la
 extern "C" mu_status mu_seeder_train_step(mu_ctx *ctx, mu_seeder *S, const uint16_t *x_bf16, const float *targets,
                                           int32_t B, float lr, int32_t update, unsigned mem, float *loss) {
   if (!ctx || !S || !x_bf16 || !targets || B < 1 || !mem_ok(mem) || S->ctx != ctx || !(lr >= 0.0f)) return MU_E_ARG;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   mu_status st = S->ensure(B);
   if (st != MU_OK) return st;
   if ((st = copy_in(ctx, S->X[0], x_bf16, (size_t)B * kCoarse * 2, mem)) != MU_OK) return st;
@@ -1053,7 +1053,7 @@ extern "C" mu_status mu_seeder_train(mu_ctx *ctx, mu_seeder *S, const mu_seed_tr
     if (ctx) set_err(ctx, "mu_seeder_train needs a seeder, batch >= 1, steps >= 1 and lr > 0");
     return MU_E_ARG;
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   const int B = o->batch;
   mu_status st = S->ensure(B);
   if (st != MU_OK) return st;
@@ -1096,7 +1096,7 @@ extern "C" mu_status mu_seed_infer(mu_ctx *ctx, const mu_seeder *Sc, int32_t n, 
     }
     src[i] = static_cast<const uint32_t *>(d->counts);
   }
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   mu_status st = S->ensure(n);
   if (st != MU_OK) return st;
   hipError_t e = hipMemcpyAsync(S->srcs, src.data(), n * sizeof(void *), hipMemcpyHostToDevice, ctx->stream);
@@ -1121,7 +1121,7 @@ extern "C" mu_status mu_seed_infer(mu_ctx *ctx, const mu_seeder *Sc, int32_t n, 
 extern "C" mu_status mu_seeder_save(const mu_seeder *S, const char *path) {
   if (!S || !path) return MU_E_ARG;
   std::vector<float> p(S->n_params), m(S->n_params), v(S->n_params);
-  hipStreamSynchronize(S->ctx->stream);
+  (void)hipStreamSynchronize(S->ctx->stream);
   if (hipMemcpy(p.data(), S->params, S->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(m.data(), S->m, S->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(v.data(), S->v, S->n_params * 4, hipMemcpyDeviceToHost) != hipSuccess)
@@ -1165,7 +1165,13 @@ extern "C" mu_status mu_seeder_load(mu_ctx *ctx, const char *path, mu_seeder **o
   mu_status st = mu_seeder_create(ctx, p.data(), out);
   if (st != MU_OK) return st;
   (*out)->step = step;
-  hipMemcpy((*out)->m, m.data(), n * 4, hipMemcpyHostToDevice);
-  hipMemcpy((*out)->v, v.data(), n * 4, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy((*out)->m, m.data(), n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((*out)->v, v.data(), n * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_err(ctx, "hipMemcpy(seeder moments): %s", hipGetErrorString(e));
+    (void)mu_seeder_destroy(*out);
+    *out = nullptr;
+    return MU_E_DEVICE;
+  }
   return MU_OK;
 }
